@@ -1,0 +1,230 @@
+"""Flow-level pins for the oracle: what the paper's analysis fixes about the
+macroscopic behaviour of the scheme, independently of how it is coded.
+
+* shear-wave decay at the rate nu k^2 / gamma = c2 (1/omega_nu - 1/2) k^2
+  (eq. 6 with eq. transport-coefficients) for waves along x, y and the
+  diagonal on rectangular grids; the diagonal wave is the one the grid
+  anisotropy corrections exist for (eq. 31, 38-39), so switching them off
+  must break it;
+* Galilean invariance of the decay on a moving background, which the cubic
+  velocity corrections (P_gamma, Q_gamma terms) restore under preconditioning;
+* the local strain-rate estimate from non-equilibrium moments (eq. 41-48)
+  against the true velocity gradient of a known flow;
+* Couette and Poiseuille channel profiles (second-order convergence);
+* lid-driven cavity: exact mass conservation, a steady state that does not
+  depend on gamma, and rectangular grids reproducing the square-grid
+  solution (the paper's own rectangular-vs-square check, Sec. 5.2).
+"""
+import numpy as np
+import pytest
+
+EX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])
+EYB = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])
+
+
+def c2_of(r):
+    q = min(1.0, r)
+    return q * q / 3.0
+
+
+def wave_setup(O, r, gamma, omega, kind, nx, ny, U0, Ub=(0.0, 0.0), corrections=7):
+    p = O.params(nx, ny, r, gamma, omega, bc=O.BC_PERIODIC, corrections=corrections)
+    X, Y = np.meshgrid(np.arange(nx) + 0.5, (np.arange(ny) + 0.5) * r)
+    Lx, Ly = nx, ny * r
+    kx = 0.0 if kind == "x" else 2 * np.pi / Lx
+    ky = 0.0 if kind == "y" else 2 * np.pi / Ly
+    kk = np.hypot(kx, ky)
+    tx, ty = ky / kk, -kx / kk          # divergence-free: t . k = 0
+    ph = kx * X + ky * Y
+    ux = Ub[0] + U0 * tx * np.sin(ph)
+    uy = Ub[1] + U0 * ty * np.sin(ph)
+    ft = O.equilibrium_field(p, 1.0, ux, uy)
+    return p, ft, (kx, ky, kk, tx, ty, ph)
+
+
+def decay_rate_error(O, r, gamma, omega, kind, nx, ny, corrections=7, Ub=(0.0, 0.0),
+                     t1=200, t2=1200):
+    p, ft, (kx, ky, kk, tx, ty, ph) = wave_setup(O, r, gamma, omega, kind, nx, ny, 1e-4,
+                                                 Ub, corrections)
+    E = np.exp(-1j * ph)
+
+    def amp():
+        _, ux, uy = O.velocity(p, ft)
+        return abs(((ux * tx + uy * ty) * E).sum())
+
+    O.step(p, ft, t1)
+    a1 = amp()
+    O.step(p, ft, t2 - t1)
+    a2 = amp()
+    rate = np.log(a1 / a2) / (t2 - t1)
+    return rate / (c2_of(r) * (1.0 / omega - 0.5) * kk ** 2) - 1.0
+
+
+GRIDS = {0.5: (32, 64), 1.0: (48, 48), 2.0: (64, 32)}
+
+
+@pytest.mark.parametrize("r", [0.5, 2.0])
+@pytest.mark.parametrize("kind", ["x", "y", "d"])
+@pytest.mark.parametrize("gamma", [1.0, 0.3])
+def test_shear_wave_decays_at_paper_viscosity(O, r, kind, gamma):
+    nx, ny = GRIDS[r]
+    err = decay_rate_error(O, r, gamma, 1.2, kind, nx, ny)
+    assert abs(err) < 2e-3, err
+
+
+@pytest.mark.parametrize("r", [0.5, 2.0])
+def test_diagonal_wave_needs_anisotropy_corrections(O, r):
+    nx, ny = GRIDS[r]
+    err = decay_rate_error(O, r, 0.5, 1.2, "d", nx, ny, corrections=0)
+    assert abs(err) > 0.5, err
+
+
+def test_galilean_invariance_under_preconditioning(O):
+    """A diagonal wave on a uniform background flow: the cubic-velocity
+    corrections keep the decay rate at its value for a fluid at rest."""
+    nx, ny = GRIDS[1.0]
+    ub = (0.04, 0.03)
+    on = decay_rate_error(O, 1.0, 0.5, 1.2, "d", nx, ny, Ub=ub)
+    off = decay_rate_error(O, 1.0, 0.5, 1.2, "d", nx, ny, Ub=ub, corrections=0)
+    assert abs(on) < 2e-3, on
+    assert abs(off) > 1e-2, off
+
+
+@pytest.mark.parametrize("r", [1.0, 2.0, 0.5])
+@pytest.mark.parametrize("gamma", [1.0, 0.3])
+def test_local_strain_rate_matches_velocity_gradient(O, r, gamma):
+    nx, ny = {1.0: (32, 32), 2.0: (32, 16), 0.5: (16, 32)}[r]
+    p, ft, (kx, ky, kk, tx, ty, ph) = wave_setup(O, r, gamma, 1.3, "d", nx, ny, 1e-3)
+    O.step(p, ft, 300)
+    f = O.stream(p, ft)
+    rho, ux, uy = O.macros(p, f)
+    amp = ((ux * tx + uy * ty) * np.sin(ph)).sum() / (np.sin(ph) ** 2).sum()
+    gx, gy = O.grad_rho(p, rho)
+    dx = np.zeros((ny, nx))
+    dy = np.zeros((ny, nx))
+    for j in range(ny):
+        for i in range(nx):
+            _, d = O.collide_node(p, f[:, j, i], gx[j, i], gy[j, i])
+            dx[j, i], dy[j, i] = d["dxux"], d["dyuy"]
+    ex = amp * tx * kx * np.cos(ph)
+    ey = amp * ty * ky * np.cos(ph)
+    assert np.abs(dx - ex).max() < 0.05 * np.abs(ex).max()
+    assert np.abs(dy - ey).max() < 0.05 * np.abs(ey).max()
+
+
+@pytest.mark.parametrize("r", [0.5, 1.0, 2.0])
+@pytest.mark.parametrize("gamma", [1.0, 0.3])
+def test_couette_profile(O, r, gamma):
+    U, ny = 0.02, 16
+    p = O.params(4, ny, r, gamma, 1.2, bc=O.BC_CHANNEL, u_lid=U)
+    ft = O.rest_state(p)
+    st, _, _ = O.solve(p, ft, 1e-13, 500, 100000)
+    assert st == 0
+    _, ux, uy = O.velocity(p, ft)
+    exact = U * (np.arange(ny) + 0.5) / ny
+    tol = 1e-9 if gamma == 1.0 else 1e-5
+    assert np.abs(ux[:, 0] - exact).max() < tol * U
+    assert np.abs(uy).max() < 1e-12
+
+
+@pytest.mark.parametrize("r,gamma", [(0.5, 1.0), (0.5, 0.3), (2.0, 0.3)])
+def test_poiseuille_second_order(O, r, gamma):
+    nu, F = 0.05, 1e-6
+    errs = []
+    for ny in (8, 16):
+        omega = 1.0 / (nu / (gamma * c2_of(r)) + 0.5)
+        p = O.params(4, ny, r, gamma, omega, bc=O.BC_CHANNEL, fx=F)
+        ft = O.rest_state(p)
+        st, _, _ = O.solve(p, ft, 1e-12, 500, 400000)
+        assert st == 0
+        _, ux, uy = O.velocity(p, ft)
+        H = ny * r
+        eta = (np.arange(ny) + 0.5) * r
+        exact = F / (2 * nu) * eta * (H - eta)
+        errs.append(np.abs(ux[:, 0] - exact).max() / exact.max())
+    assert errs[1] < 0.03
+    assert 3.6 < errs[0] / errs[1] < 4.4, errs
+
+
+def test_stream_conserves_mass_with_moving_lid(O):
+    rng = np.random.default_rng(1)
+    for r in (0.5, 2.0):
+        p = O.params(7, 5, r, 1.0, 1.0, u_lid=0.07)
+        ft = O.rest_state(p) * (1 + 0.2 * rng.uniform(-1, 1, (9, 5, 7)))
+        f = O.stream(p, ft)
+        assert abs(f.sum() - ft.sum()) < 1e-13
+
+
+@pytest.mark.parametrize("r", [0.5, 1.0, 2.0])
+def test_lid_bounce_back_closed_form(O, r):
+    """Ladd's moving-wall rule, delta_a = 2 w_a rho_w (e_a . u_w) / c2 with the
+    x-variance c2 of the rest weights w_a; at r = 1 it is rho U / 6 for the
+    diagonal links.  Top-row populations entering from the lid after one
+    streaming of the rest state."""
+    U = 0.03
+    p = O.params(6, 5, r, 1.0, 1.0, u_lid=U)
+    w = O.rest_populations(p)
+    c2 = c2_of(r)
+    f = O.stream(p, O.rest_state(p))
+    top = f[:, -1, :]
+    d5 = 2 * w[5] * 1.0 * (1 * U) / c2
+    d6 = 2 * w[6] * 1.0 * (-1 * U) / c2
+    np.testing.assert_allclose(top[7], w[7] - d5, rtol=1e-14)   # from f~5
+    np.testing.assert_allclose(top[8], w[8] - d6, rtol=1e-14)   # from f~6
+    np.testing.assert_allclose(top[4], w[4], rtol=1e-14)
+    if r == 1.0:
+        assert abs(d5 - U / 6.0) < 1e-15
+    # everything below the top row is untouched rest state
+    np.testing.assert_allclose(f[:, :-1, :], O.rest_state(p)[:, :-1, :], rtol=1e-14)
+
+
+def test_cavity_conserves_mass(O):
+    p = O.with_re(O.params(24, 12, 2.0, 0.3, 1.0, u_lid=0.05), 100)
+    ft = O.rest_state(p)
+    m0 = ft.sum()
+    O.step(p, ft, 2000)
+    assert abs(ft.sum() / m0 - 1) < 1e-13
+
+
+def _cavity(O, nx, ny, r, gamma, re, U, corrections=7):
+    p = O.with_re(O.params(nx, ny, r, gamma, 1.0, u_lid=U, corrections=corrections), re)
+    ft = O.rest_state(p)
+    st, n, _ = O.solve(p, ft, 1e-9, 500, 200000)
+    assert st == 0
+    _, ux, uy = O.velocity(p, ft)
+    # centre lines: u_x(y) at x = L/2 and u_y(x) at y = H/2 (even counts: mean
+    # of the two middle nodes), positions in units of dx, wall values added
+    L, H = nx, ny * r
+    yu = np.r_[0.0, (np.arange(ny) + 0.5) * r, H]
+    cu = np.r_[0.0, 0.5 * (ux[:, nx // 2 - 1] + ux[:, nx // 2]) / U, 1.0]
+    xv = np.r_[0.0, np.arange(nx) + 0.5, L]
+    cv = np.r_[0.0, 0.5 * (uy[ny // 2 - 1, :] + uy[ny // 2, :]) / U, 0.0]
+    return (yu, cu), (xv, cv), n
+
+
+def test_cavity_steady_state_independent_of_gamma(O):
+    U = 0.04
+    (yu1, cu1), (xv1, cv1), n1 = _cavity(O, 32, 32, 1.0, 1.0, 20, U)
+    (yu2, cu2), (xv2, cv2), n2 = _cavity(O, 32, 32, 1.0, 0.5, 20, U)
+    assert np.abs(cu1 - cu2).max() < 3e-3
+    assert np.abs(cv1 - cv2).max() < 3e-3
+    assert n2 < n1          # and preconditioning converges in fewer steps
+
+
+@pytest.mark.parametrize("nx,ny,r", [(32, 16, 2.0), (32, 20, 1.6), (32, 64, 0.5)])
+def test_rectangular_grid_reproduces_square_grid(O, nx, ny, r):
+    """Square cavity of side 32 dx at Re = 50, Ma = 0.06 (U = Ma q c_*), gamma
+    = 0.5: centre-line profiles on the rectangular grid match the square grid."""
+    ma, cs = 0.06, 1.0 / np.sqrt(3.0)
+    (ys, us), (xs, vs), _ = _cavity(O, 32, 32, 1.0, 0.5, 50, ma * cs)
+    (yr, ur), (xr, vr), _ = _cavity(O, nx, ny, r, 0.5, 50, ma * cs * min(1.0, r))
+    eu = np.abs(ur - np.interp(yr, ys, us)).max()
+    ev = np.abs(vr - np.interp(xr, xs, vs)).max()
+    assert eu < 0.02 and ev < 0.02, (eu, ev)
+
+
+def test_rectangular_grid_without_corrections_disagrees(O):
+    ma, cs = 0.06, 1.0 / np.sqrt(3.0)
+    (ys, us), _, _ = _cavity(O, 32, 32, 1.0, 0.5, 50, ma * cs)
+    (yr, ur), _, _ = _cavity(O, 32, 16, 2.0, 0.5, 50, ma * cs, corrections=0)
+    assert np.abs(ur - np.interp(yr, ys, us)).max() > 0.05
