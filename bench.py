@@ -1,0 +1,192 @@
+"""Throughput benchmark of the PRC-LBM hot path on one MI355X.
+
+One "step" is one fused time step (streaming with boundaries, fields, density
+gradient, collision) over the whole grid; the FP64 residual/mass reduction
+that decides convergence runs every 1000 steps inside the timed region, as in
+a solve.  Workload: lid-driven cavity 1024 x 512, r = 2, Re = 1000, U = 0.05,
+gamma = 0.1, FP32 deviation storage, from the fluid at rest.  Prints one JSON
+line on stdout (progress goes to stderr).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads  # noqa: E402
+
+BYTES_PER_NODE = {"f64": 144, "f32": 72, "f16": 36, "bf16": 36}
+STORAGE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
+HBM_PEAK_GBS = 8000.0
+CHECK_EVERY = 1000
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_gpu(w: workloads.Cavity, steps: int, warmup: int):
+    import torch
+    from paper_2208_03562_amd import solver
+
+    p = solver.make_params(w.nx, w.ny, w.r, w.gamma, re=w.re, u_lid=w.u_lid,
+                           storage=STORAGE[w.storage])
+    stream = torch.cuda.Stream()
+    sol = solver.Solver(p, device="cuda:0", stream=stream)
+    sol.residual()  # velocity snapshot of the initial state
+    diverged_at = None
+    done = 0
+    while done < warmup:
+        n = min(CHECK_EVERY, warmup - done)
+        sol.step(n)
+        done += n
+        if done % CHECK_EVERY == 0:
+            out = sol.residual()
+            R = (out[0] / out[1]) ** 0.5 if out[1] > 0 else 0.0
+            if diverged_at is None and not (math.isfinite(R) and out[3] < 1.0):
+                diverged_at = done
+    torch.cuda.synchronize()
+    log(f"[bench] {w.name}: warmup {warmup} steps done")
+
+    ev = []
+    hist = []
+    t0 = time.perf_counter()
+    done = 0
+    while done < steps:
+        n = min(CHECK_EVERY, steps - done)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        sol.step(n)
+        b.record(stream)
+        ev.append((a, b, n))
+        done += n
+        if done % CHECK_EVERY == 0:
+            out = sol.residual()  # synchronises the stream
+            R = (out[0] / out[1]) ** 0.5 if out[1] > 0 else 0.0
+            hist.append(R)
+            if diverged_at is None and not (math.isfinite(R) and out[3] < 1.0):
+                diverged_at = warmup + done
+    stream.synchronize()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sweep_ms = sum(a.elapsed_time(b) for a, b, _ in ev)
+    sweep_n = sum(n for _, _, n in ev)
+    nodes = w.nx * w.ny
+    wall = t1 - t0
+    res = dict(
+        wall_s=wall,
+        mlups=nodes * steps / wall / 1e6,
+        ms_per_step=wall * 1e3 / steps,
+        sweep_us=sweep_ms * 1e3 / sweep_n,
+        residual_last=(hist[-1] if math.isfinite(hist[-1]) else str(hist[-1])) if hist else None,
+        diverged_at=diverged_at,
+    )
+    res["sweep_gbs"] = BYTES_PER_NODE[w.storage] * nodes / (res["sweep_us"] * 1e-6) / 1e9
+    log(f"[bench] {w.name}: {steps} steps in {wall:.3f} s -> {res['mlups']:.0f} MLUPS, "
+        f"sweep {res['sweep_us']:.2f} us ({res['sweep_gbs']:.0f} GB/s)")
+    del sol
+    torch.cuda.empty_cache()
+    return res
+
+
+def run_cpu_baseline(w: workloads.Cavity, budget_s: float):
+    import numpy as np  # noqa: F401
+    from oracle import oracle as O
+
+    po = O.with_re(O.params(w.nx, w.ny, w.r, w.gamma, 1.0, u_lid=w.u_lid), w.re)
+    ft = O.rest_state(po)
+    t0 = time.perf_counter()
+    O.step(po, ft, 1)
+    one = time.perf_counter() - t0
+    n = max(2, int(budget_s / max(one, 1e-6)))
+    t0 = time.perf_counter()
+    O.step(po, ft, n)
+    dt = time.perf_counter() - t0
+    log(f"[bench] oracle: {n} steps of {w.nx}x{w.ny} in {dt:.2f} s")
+    return dict(value=w.nx * w.ny * n / dt / 1e6, unit="MLUPS", cores=O.threads(),
+                kind="oracle",
+                sample=f"{n} FP64 steps of the {w.nx}x{w.ny} cavity from rest "
+                       f"(after 1 untimed step), OpenMP over rows")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=2000)
+    ap.add_argument("--cpu-budget", type=float, default=12.0,
+                    help="seconds of oracle work for the CPU baseline (0: skip)")
+    ap.add_argument("--hbm-steps", type=int, default=2000,
+                    help="steps on the 4096x2048 FP32 grid (0: skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the method has no "
+              "multi-GPU path in this library", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    w = workloads.CAVITY_1024x512_F32
+    main_res = run_gpu(w, args.steps, args.warmup)
+    wc = workloads.CAVITY_1024x512_F32_MA006
+    comp = run_gpu(wc, args.steps, args.warmup)
+    hbm = None
+    if args.hbm_steps > 0:
+        wh = workloads.CAVITY_4096x2048_F32
+        r = run_gpu(wh, args.hbm_steps, min(args.warmup, 500))
+        hbm = dict(workload=wh.name, nx=wh.nx, ny=wh.ny, mlups=round(r["mlups"], 1),
+                   sweep_us=round(r["sweep_us"], 2), achieved_gbs=round(r["sweep_gbs"], 1),
+                   frac=round(r["sweep_gbs"] / HBM_PEAK_GBS, 4),
+                   bytes_per_node=BYTES_PER_NODE[wh.storage])
+    cpu = run_cpu_baseline(w, args.cpu_budget) if args.cpu_budget > 0 else None
+
+    out = {
+        "metric": "MLUPS",
+        "value": round(main_res["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_res["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "r": w.r, "re": w.re,
+                   "u_lid": w.u_lid, "gamma": w.gamma, "storage": "f32 deviations",
+                   "residual_every": CHECK_EVERY, "bytes_per_node": BYTES_PER_NODE[w.storage]},
+        "roofline": {"bound": "hbm", "achieved": round(main_res["sweep_gbs"], 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(main_res["sweep_gbs"] / HBM_PEAK_GBS, 4),
+                     "traffic": None, "kernel": "k_sweep", "kernel_us": round(main_res["sweep_us"], 3),
+                     "note": "72 B/node (9 FP32 reads + 9 FP32 writes); the 37.7 MB working set "
+                             "is cache-resident"},
+        "solution": {"diverged_at_step": main_res["diverged_at"],
+                     "residual_last": main_res["residual_last"],
+                     "note": "U = 0.05 with gamma = 0.1 is outside the scheme's stable range; "
+                             "the FP64 oracle diverges at the same step. Throughput is "
+                             "data-independent (branch-free sweep)."},
+        "stable_companion": {"workload": wc.name, "u_lid": round(wc.u_lid, 6),
+                             "mlups": round(comp["mlups"], 1),
+                             "sweep_us": round(comp["sweep_us"], 3),
+                             "achieved_gbs": round(comp["sweep_gbs"], 1),
+                             "residual_last": comp["residual_last"],
+                             "diverged_at_step": comp["diverged_at"]},
+        "hbm_grid": hbm,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,183 @@
+/*
+ * prc.h -- C ABI of the MI355X (gfx950) library for the preconditioned
+ * rectangular central-moment lattice Boltzmann method (PRC-LBM) of
+ * E. Yahia and K. N. Premnath, arXiv 2208.03562.
+ *
+ * The library solves the preconditioned Navier-Stokes equations (Sec. 3,
+ * eq. 5-6) on a two-dimensional rectangular D2Q9 grid with aspect ratio
+ * r = dy/dx (Sec. 2).  One time step is the algorithm of Appendix A: central
+ * moments, relaxation to gamma-preconditioned equilibria extended by the
+ * grid-anisotropy and cubic-velocity corrections (Sec. 3.5, eq. 38-40) whose
+ * velocity gradients come from non-equilibrium moments (Sec. 3.6, eq. 41-48),
+ * back to populations, then streaming with no-slip walls and a moving lid.
+ *
+ * Conventions for every entry point:
+ *  - Every call returns prc_status; nothing throws across the ABI.  On an
+ *    error, prc_last_error() returns a message for the calling thread.
+ *  - All state buffers are device memory allocated and owned by the caller;
+ *    the library keeps no pointer after a call returns and allocates no
+ *    device memory of its own (except the cached launch graphs of
+ *    prc_step, which live until prc_release_graphs or process exit).
+ *  - Calls are ordered on the HIP stream passed in (0 = null stream) and are
+ *    asynchronous unless stated otherwise.
+ *  - Arguments are validated on the host before anything is launched;
+ *    invalid input returns PRC_EINVAL and launches nothing.
+ *
+ * State layout ("population state"): nine planes, plane a holding
+ * population a in the velocity order of Sec. 2 eq. 3a/3b
+ * (0 rest, 1 E, 2 N, 3 W, 4 S, 5 NE, 6 NW, 7 SW, 8 SE).  Element (a, j, i)
+ * -- node i along x in [0, nx), row j along y in [0, ny) -- sits at element
+ * offset a * plane + j * pitch + i, with pitch and plane from prc_layout().
+ * The stored value is the DEVIATION f_a - rho0 * w_a of the post-collision
+ * population from the rest state (w_a: product of the one-dimensional rest
+ * weights of variance c_s^2 along x and c_s^2 / r^2 along y, c_s^2 = q^2/3,
+ * q = min(1, r), eq. 2), in the element type given by prc_params.storage.
+ * A buffer of all zeros is the fluid at rest with density rho0.
+ */
+#ifndef PRC_H
+#define PRC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PRC_OK = 0,
+    PRC_NOT_CONVERGED = 1, /* step limit reached; not an error */
+    PRC_EINVAL = -1,       /* invalid argument; nothing launched */
+    PRC_EHIP = -2,         /* a HIP call failed; message has hipGetErrorString */
+    PRC_EDIVERGED = -3,    /* non-finite residual/mass or |u| >= 1 */
+    PRC_ENOMEM = -4        /* host allocation failed */
+} prc_status;
+
+typedef enum {
+    PRC_BC_CAVITY = 0,   /* walls on all four sides, lid on top (y = ny r) */
+    PRC_BC_PERIODIC = 1, /* periodic in x and y */
+    PRC_BC_CHANNEL = 2   /* periodic in x; wall at y = 0, lid at y = ny r */
+} prc_bc;
+
+typedef enum {
+    PRC_F64 = 0,  /* double deviations, double arithmetic */
+    PRC_F32 = 1,  /* float deviations, float arithmetic */
+    PRC_F16 = 2,  /* IEEE half deviations, float arithmetic */
+    PRC_BF16 = 3  /* bfloat16 deviations, float arithmetic */
+} prc_storage;
+
+typedef enum {
+    PRC_CORR_THETA = 1,  /* velocity-gradient terms of k2s, k2d (eq. 38, 39) */
+    PRC_CORR_LAMBDA = 2, /* density-gradient terms of k2s, k2d (eq. 38, 39) */
+    PRC_CORR_K11 = 4,    /* correction terms of k11 (eq. 40) */
+    PRC_CORR_ALL = 7     /* the method; the others exist for tests */
+} prc_corrections;
+
+typedef enum {
+    PRC_FRAME_CENTRAL = 0, /* PRC-LBM: relax central moments (Sec. 4.2) */
+    PRC_FRAME_RAW = 1      /* PRNR-LBM: relax raw moments (Sec. 4.1, Sec. 6) */
+} prc_frame;
+
+/* Problem description (Sec. 2-5).  Lattice units: dx = dt = 1, dy = r. */
+typedef struct {
+    int32_t nx, ny;     /* nodes along x and y, each >= 3 */
+    double r;           /* grid aspect ratio dy/dx > 0 (Sec. 2) */
+    double gamma;       /* preconditioning parameter, 0 < gamma <= 1 (eq. 6) */
+    double omega_nu;    /* shear relaxation rate: k2d, k11 (Appendix A) */
+    double omega_xi;    /* bulk relaxation rate: k2s; the paper uses 1 */
+    double omega_1;     /* first-order central moments; the paper uses 1 */
+    double omega_3;     /* k21, k12; the paper uses 1 */
+    double omega_4;     /* k22; the paper uses 1 */
+    double u_lid;       /* lid velocity along +x; |u_lid| < q / sqrt(3) */
+    double fx, fy;      /* uniform body force (eq. 6) */
+    double rho0;        /* reference density: rest state and wall density */
+    int32_t bc;         /* prc_bc */
+    int32_t storage;    /* prc_storage */
+    int32_t corrections;/* prc_corrections bitmask, normally PRC_CORR_ALL */
+    int32_t frame;      /* prc_frame, normally PRC_FRAME_CENTRAL */
+} prc_params;
+
+/* Fill *p with the method's defaults: rates omega_xi = omega_1 = omega_3 =
+ * omega_4 = 1 (Appendix A, below the relaxation sub-step), omega_nu = 1,
+ * gamma = 1, r = 1, rho0 = 1, no lid, no force, cavity, FP32 storage, all
+ * corrections, central frame; nx, ny must still be set.  Host only. */
+prc_status prc_params_default(prc_params *p);
+
+/* Set p->omega_nu from the Reynolds number Re = U H / nu of Sec. 5 with the
+ * cavity height H = ny * r (units of dx) and U = p->u_lid, inverting
+ * nu = gamma q^2 c_*^2 (1/omega_nu - 1/2) (eq. transport-coefficients).
+ * EINVAL if re <= 0, u_lid == 0 or the resulting omega_nu is not in (0, 2).
+ * Host only. */
+prc_status prc_params_from_re(prc_params *p, double re);
+
+/* Check *p against the rules above without touching the GPU. Host only. */
+prc_status prc_validate(const prc_params *p);
+
+/* Element pitch of one row and element stride of one plane of the population
+ * state (see the layout above).  Host only. */
+prc_status prc_layout(const prc_params *p, int64_t *pitch, int64_t *plane);
+
+/* Bytes of one population state buffer (9 planes); 0 if *p is invalid. */
+size_t prc_state_bytes(const prc_params *p);
+
+/* Bytes of the scratch buffer that prc_residual and prc_solve need. */
+size_t prc_scratch_bytes(const prc_params *p);
+
+/* Write the rest state (all deviations zero, Sec. 5: fluid at rest with
+ * density rho0) into f, padding included.  f: device, prc_state_bytes. */
+prc_status prc_init(const prc_params *p, void *f, hipStream_t stream);
+
+/* Advance nsteps >= 0 time steps of Appendix A.  Each step reads one state
+ * buffer and writes the other: step k (k = 0, 1, ...) reads f_a when k is
+ * even and f_b when k is odd, so after nsteps steps the newest state is in
+ * f_a when nsteps is even and in f_b when it is odd.  One step = streaming
+ * with boundaries (Appendix A, "stream"; moving-wall bounce-back as noted at
+ * the end of Appendix A), the hydrodynamic fields of the streamed state
+ * (eq. hydrodynamicfields), the density gradient, and the collision.  f_a and
+ * f_b: distinct device buffers of prc_state_bytes, 256-byte aligned. */
+prc_status prc_step(const prc_params *p, void *f_a, void *f_b, int64_t nsteps,
+                    hipStream_t stream);
+
+/* Convergence check (Sec. 5.2: L2 norm of the change of the velocity between
+ * checks).  Computes, in double precision, from the fields of state f:
+ *   out[0] = sum_nodes |u - u_prev|^2     out[1] = sum_nodes |u|^2
+ *   out[2] = sum_nodes rho                out[3] = max_nodes |u|^2
+ * then overwrites u_prev with u.  The relative residual is
+ * sqrt(out[0] / out[1]).  u_prev: device double[2][ny][nx] (u_x plane, then
+ * u_y plane); scratch: device, prc_scratch_bytes; out: host double[4].
+ * Synchronises the stream.  The sums are reproduced bit for bit run to run. */
+prc_status prc_residual(const prc_params *p, const void *f, double *u_prev,
+                        void *scratch, double out[4], hipStream_t stream);
+
+/* Hydrodynamic fields of state f (eq. hydrodynamicfields after streaming):
+ * rho, u_x, u_y as device double[ny][nx] arrays (row j at offset j * nx).
+ * Any of the three output pointers may be NULL. */
+prc_status prc_macros(const prc_params *p, const void *f, double *rho,
+                      double *ux, double *uy, hipStream_t stream);
+
+/* Run from the state in f_a until the relative residual over check_every
+ * steps falls below tol, or max_steps is reached.  u_prev is first set from
+ * the initial state; after every check_every steps prc_residual is taken and
+ * its relative residual appended to hist (host double[hist_cap]; may be NULL).
+ * The newest state is in f_a when *steps_out is even, else in f_b.
+ * Returns PRC_OK (converged), PRC_NOT_CONVERGED, or PRC_EDIVERGED when a
+ * residual or the mass is not finite or max |u| >= 1 (lattice speed).
+ * Synchronises the stream at every check. */
+prc_status prc_solve(const prc_params *p, void *f_a, void *f_b, double *u_prev,
+                     void *scratch, double tol, int64_t check_every,
+                     int64_t max_steps, int64_t *steps_out, double *hist,
+                     int64_t hist_cap, int64_t *hist_len, hipStream_t stream);
+
+/* Drop the launch graphs cached by prc_step (they hold no user memory). */
+prc_status prc_release_graphs(void);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *prc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PRC_H */

@@ -63,6 +63,7 @@ def lib():
         L = ctypes.CDLL(LIB)
         dp = ctypes.POINTER(ctypes.c_double)
         pp = ctypes.POINTER(Params)
+        L.orc_threads.restype = ctypes.c_int
         L.orc_lattice.argtypes = [ctypes.c_double, dp, dp]
         L.orc_omega_nu_from_re.argtypes = [pp, ctypes.c_double]
         L.orc_omega_nu_from_re.restype = ctypes.c_double
@@ -112,6 +113,10 @@ def with_re(p: Params, re: float) -> Params:
     q = Params.from_buffer_copy(p)
     q.omega_nu = lib().orc_omega_nu_from_re(ctypes.byref(q), float(re))
     return q
+
+
+def threads() -> int:
+    return int(lib().orc_threads())
 
 
 def lattice(r: float):

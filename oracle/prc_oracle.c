@@ -29,6 +29,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* Sec. 2 eq. 3a/3b (e_y in units of r) */
 static const int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
@@ -40,6 +43,15 @@ enum { K00 = 0, K10, K01, K20, K02, K11, K21, K12, K22 };
 
 #define IDX(p, a, i, j) ((size_t)(a) * (size_t)(p)->nx * (size_t)(p)->ny + \
                          (size_t)(j) * (size_t)(p)->nx + (size_t)(i))
+
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 void orc_lattice(double r, double *q, double *c2)
 {
@@ -403,7 +415,7 @@ void orc_stream(const orc_params *p, const double *ft, double *f)
     const int nx = p->nx, ny = p->ny;
     const int px = p->bc == ORC_BC_PERIODIC || p->bc == ORC_BC_CHANNEL;
     const int py = p->bc == ORC_BC_PERIODIC;
-#pragma omp parallel for schedule(static) if ((long)nx * ny > 16384)
+#pragma omp parallel for schedule(static) if ((long)nx * ny > 4096)
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i)
             for (int a = 0; a < 9; ++a) {
@@ -499,7 +511,7 @@ int orc_step(const orc_params *p, double *ft, int64_t nsteps)
         orc_stream(p, ft, f);
         orc_macros(p, f, rho, ux, uy);
         orc_grad_rho(p, rho, gx, gy);
-#pragma omp parallel for schedule(static) if ((long)nx * ny > 16384)
+#pragma omp parallel for schedule(static) if ((long)nx * ny > 4096)
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
                 double fn[9], fo[9];

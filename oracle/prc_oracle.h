@@ -56,6 +56,9 @@ typedef struct {
 /* number of per-node diagnostics written by orc_collide_node */
 #define ORC_NDIAG 8
 
+/* threads the loops over nodes may use (OpenMP), 1 without OpenMP */
+int orc_threads(void);
+
 /* Sec. 2, eq. 2: q = min(1, r), c_s^2 = q^2 c_*^2 with c_*^2 = 1/3 */
 void orc_lattice(double r, double *q, double *c2);
 

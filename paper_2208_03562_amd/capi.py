@@ -1,0 +1,190 @@
+"""ctypes binding of the C ABI in ``include/prc.h`` (``libprc.so``).
+
+Argument marshalling only: every function here forwards to the entry point of
+the same name, and every step of the method runs in the library's HIP
+kernels.  Device pointers are plain integers (e.g. ``tensor.data_ptr()``) and
+streams are ``hipStream_t`` handles (``torch.cuda.Stream.cuda_stream``; 0 is
+the null stream).  A missing or stale library raises at import of
+:func:`lib` -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libprc.so")
+
+# prc_status
+PRC_OK, PRC_NOT_CONVERGED, PRC_EINVAL, PRC_EHIP, PRC_EDIVERGED, PRC_ENOMEM = 0, 1, -1, -2, -3, -4
+STATUS_NAMES = {0: "PRC_OK", 1: "PRC_NOT_CONVERGED", -1: "PRC_EINVAL", -2: "PRC_EHIP",
+                -3: "PRC_EDIVERGED", -4: "PRC_ENOMEM"}
+# prc_bc
+PRC_BC_CAVITY, PRC_BC_PERIODIC, PRC_BC_CHANNEL = 0, 1, 2
+# prc_storage
+PRC_F64, PRC_F32, PRC_F16, PRC_BF16 = 0, 1, 2, 3
+STORAGE_BYTES = {PRC_F64: 8, PRC_F32: 4, PRC_F16: 2, PRC_BF16: 2}
+# prc_corrections
+PRC_CORR_THETA, PRC_CORR_LAMBDA, PRC_CORR_K11, PRC_CORR_ALL = 1, 2, 4, 7
+# prc_frame
+PRC_FRAME_CENTRAL, PRC_FRAME_RAW = 0, 1
+
+
+class prc_params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("r", ctypes.c_double), ("gamma", ctypes.c_double),
+        ("omega_nu", ctypes.c_double), ("omega_xi", ctypes.c_double),
+        ("omega_1", ctypes.c_double), ("omega_3", ctypes.c_double),
+        ("omega_4", ctypes.c_double),
+        ("u_lid", ctypes.c_double), ("fx", ctypes.c_double), ("fy", ctypes.c_double),
+        ("rho0", ctypes.c_double),
+        ("bc", ctypes.c_int32), ("storage", ctypes.c_int32),
+        ("corrections", ctypes.c_int32), ("frame", ctypes.c_int32),
+    ]
+
+    def copy(self) -> "prc_params":
+        return prc_params.from_buffer_copy(self)
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class PrcError(RuntimeError):
+    def __init__(self, fn: str, status: int, msg: str):
+        super().__init__(f"{fn} -> {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_P = ctypes.POINTER(prc_params)
+_VP = ctypes.c_void_p
+_DP = ctypes.c_void_p  # double* (device or host, passed as an address)
+_I64P = ctypes.POINTER(ctypes.c_int64)
+
+_PROTOS = {
+    "prc_params_default": (ctypes.c_int, [_P]),
+    "prc_params_from_re": (ctypes.c_int, [_P, ctypes.c_double]),
+    "prc_validate": (ctypes.c_int, [_P]),
+    "prc_layout": (ctypes.c_int, [_P, _I64P, _I64P]),
+    "prc_state_bytes": (ctypes.c_size_t, [_P]),
+    "prc_scratch_bytes": (ctypes.c_size_t, [_P]),
+    "prc_init": (ctypes.c_int, [_P, _VP, _VP]),
+    "prc_step": (ctypes.c_int, [_P, _VP, _VP, ctypes.c_int64, _VP]),
+    "prc_residual": (ctypes.c_int, [_P, _VP, _DP, _VP, ctypes.POINTER(ctypes.c_double), _VP]),
+    "prc_macros": (ctypes.c_int, [_P, _VP, _DP, _DP, _DP, _VP]),
+    "prc_solve": (ctypes.c_int, [_P, _VP, _VP, _DP, _VP, ctypes.c_double, ctypes.c_int64,
+                                 ctypes.c_int64, _I64P, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.c_int64, _I64P, _VP]),
+    "prc_release_graphs": (ctypes.c_int, []),
+    "prc_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load ``libprc.so`` (built in-tree by ``__graft_entry__.build()``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "(there is no fallback implementation)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _PROTOS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_names():
+    return list(_PROTOS)
+
+
+def last_error() -> str:
+    return (lib().prc_last_error() or b"").decode()
+
+
+def _check(fn: str, st: int, ok=(PRC_OK,)) -> int:
+    if st not in ok:
+        raise PrcError(fn, st, last_error())
+    return st
+
+
+# ---- same-named wrappers -------------------------------------------------
+
+def prc_params_default() -> prc_params:
+    p = prc_params()
+    _check("prc_params_default", lib().prc_params_default(ctypes.byref(p)))
+    return p
+
+
+def prc_params_from_re(p: prc_params, re: float) -> prc_params:
+    _check("prc_params_from_re", lib().prc_params_from_re(ctypes.byref(p), float(re)))
+    return p
+
+
+def prc_validate(p: prc_params) -> None:
+    _check("prc_validate", lib().prc_validate(ctypes.byref(p)))
+
+
+def prc_layout(p: prc_params):
+    pitch, plane = ctypes.c_int64(), ctypes.c_int64()
+    _check("prc_layout", lib().prc_layout(ctypes.byref(p), ctypes.byref(pitch),
+                                          ctypes.byref(plane)))
+    return pitch.value, plane.value
+
+
+def prc_state_bytes(p: prc_params) -> int:
+    n = lib().prc_state_bytes(ctypes.byref(p))
+    if n == 0:
+        raise PrcError("prc_state_bytes", PRC_EINVAL, last_error())
+    return n
+
+
+def prc_scratch_bytes(p: prc_params) -> int:
+    n = lib().prc_scratch_bytes(ctypes.byref(p))
+    if n == 0:
+        raise PrcError("prc_scratch_bytes", PRC_EINVAL, last_error())
+    return n
+
+
+def prc_init(p: prc_params, f: int, stream: int = 0) -> None:
+    _check("prc_init", lib().prc_init(ctypes.byref(p), f, stream))
+
+
+def prc_step(p: prc_params, f_a: int, f_b: int, nsteps: int, stream: int = 0) -> None:
+    _check("prc_step", lib().prc_step(ctypes.byref(p), f_a, f_b, int(nsteps), stream))
+
+
+def prc_residual(p: prc_params, f: int, u_prev: int, scratch: int, stream: int = 0):
+    out = (ctypes.c_double * 4)()
+    _check("prc_residual", lib().prc_residual(ctypes.byref(p), f, u_prev, scratch, out, stream))
+    return list(out)
+
+
+def prc_macros(p: prc_params, f: int, rho: int | None, ux: int | None, uy: int | None,
+               stream: int = 0) -> None:
+    _check("prc_macros", lib().prc_macros(ctypes.byref(p), f, rho, ux, uy, stream))
+
+
+def prc_solve(p: prc_params, f_a: int, f_b: int, u_prev: int, scratch: int, tol: float,
+              check_every: int, max_steps: int, hist_cap: int = 4096, stream: int = 0):
+    """Returns (status, steps, residual history); status is PRC_OK,
+    PRC_NOT_CONVERGED or PRC_EDIVERGED (other statuses raise)."""
+    steps, nh = ctypes.c_int64(), ctypes.c_int64()
+    hist = (ctypes.c_double * max(1, hist_cap))()
+    st = lib().prc_solve(ctypes.byref(p), f_a, f_b, u_prev, scratch, float(tol),
+                         int(check_every), int(max_steps), ctypes.byref(steps), hist,
+                         int(hist_cap), ctypes.byref(nh), stream)
+    _check("prc_solve", st, ok=(PRC_OK, PRC_NOT_CONVERGED, PRC_EDIVERGED))
+    return st, steps.value, list(hist[: min(nh.value, hist_cap)])
+
+
+def prc_release_graphs() -> None:
+    _check("prc_release_graphs", lib().prc_release_graphs())
+
+
+def prc_last_error() -> str:
+    return last_error()

@@ -1,0 +1,506 @@
+// C ABI and kernels of the PRC-LBM library for MI355X (gfx950).
+//
+// Kernels:
+//   k_sweep     one fused time step: pull with boundaries, fields, density
+//               gradient from an LDS tile of densities, collision, store
+//   k_macros    fields of a state (for output)
+//   k_residual  per-block FP64 partial sums of the convergence check
+//   k_finish    fixed-order reduction of the partial sums
+// The ABI is declared and documented in include/prc.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "prc.h"
+#include "prc_coef.hpp"
+#include "prc_device.hpp"
+
+namespace prc {
+
+// ---------------------------------------------------------------- errors --
+static thread_local std::string g_err;
+
+static prc_status fail(prc_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+static prc_status fail(prc_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(PRC_EHIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_),         \
+                        __FILE__, __LINE__);                                             \
+    } while (0)
+
+// ---------------------------------------------------------------- layout --
+constexpr int kPitchAlignBytes = 256;
+constexpr int kSweepTX = 64;   // one wavefront per tile row
+constexpr int kSweepTY = 4;
+constexpr int kRedBlock = 256;
+constexpr int kRedMaxBlocks = 1024;
+
+static size_t elem_bytes(int storage)
+{
+    switch (storage) {
+    case PRC_F64: return 8;
+    case PRC_F32: return 4;
+    default: return 2;
+    }
+}
+
+static void layout(const prc_params &p, int64_t &pitch, int64_t &plane)
+{
+    const int64_t per = kPitchAlignBytes / (int64_t)elem_bytes(p.storage);
+    pitch = ((int64_t)p.nx + per - 1) / per * per;
+    plane = pitch * p.ny;
+}
+
+static prc_status validate(const prc_params *p)
+{
+    if (!p) return fail(PRC_EINVAL, "params is NULL");
+    if (p->nx < 3 || p->ny < 3) return fail(PRC_EINVAL, "nx, ny must be >= 3 (got %d, %d)", p->nx, p->ny);
+    if ((int64_t)p->nx * p->ny > ((int64_t)1 << 30))
+        return fail(PRC_EINVAL, "grid too large (%d x %d)", p->nx, p->ny);
+    if (!(p->r > 0.0) || !std::isfinite(p->r)) return fail(PRC_EINVAL, "r must be > 0");
+    if (!(p->gamma > 0.0 && p->gamma <= 1.0)) return fail(PRC_EINVAL, "gamma must be in (0, 1]");
+    const double om[5] = {p->omega_nu, p->omega_xi, p->omega_1, p->omega_3, p->omega_4};
+    for (double w : om)
+        if (!(w > 0.0 && w < 2.0)) return fail(PRC_EINVAL, "relaxation rates must be in (0, 2)");
+    const double q = p->r < 1.0 ? p->r : 1.0;
+    if (!(std::fabs(p->u_lid) < q / std::sqrt(3.0)))
+        return fail(PRC_EINVAL, "|u_lid| must be below the sound speed q/sqrt(3)");
+    if (!std::isfinite(p->fx) || !std::isfinite(p->fy)) return fail(PRC_EINVAL, "force not finite");
+    if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) return fail(PRC_EINVAL, "rho0 must be > 0");
+    if (p->bc < PRC_BC_CAVITY || p->bc > PRC_BC_CHANNEL) return fail(PRC_EINVAL, "unknown bc %d", p->bc);
+    if (p->storage < PRC_F64 || p->storage > PRC_BF16)
+        return fail(PRC_EINVAL, "unknown storage %d", p->storage);
+    if (p->corrections < 0 || p->corrections > PRC_CORR_ALL)
+        return fail(PRC_EINVAL, "corrections bitmask out of range");
+    if (p->frame != PRC_FRAME_CENTRAL)
+        return fail(PRC_EINVAL, "frame %d is not available in this library", p->frame);
+    return PRC_OK;
+}
+
+static prc_status check_buf(const void *b, const char *name)
+{
+    if (!b) return fail(PRC_EINVAL, "%s is NULL", name);
+    if ((uintptr_t)b % 256 != 0) return fail(PRC_EINVAL, "%s is not 256-byte aligned", name);
+    return PRC_OK;
+}
+
+// ------------------------------------------------------------- kernels --
+
+// XCD-aware tile order: the hardware hands workgroup i to XCD i mod 8, so
+// workgroup i takes logical tile (i mod 8) * per + i / 8.  Each XCD then owns
+// one contiguous band of tile rows, and the density halo a tile shares with
+// the tiles above and below it is read through the same L2.
+__device__ __forceinline__ bool map_tile(int tiles, int per, int &tile)
+{
+    const int i = blockIdx.x;
+    tile = (i % kXcds) * per + i / kXcds;
+    return tile < tiles;
+}
+
+template <typename ST, typename CT, int BC, int TX, int TY>
+__global__ void __launch_bounds__(TX *TY)
+    k_sweep(const ST *__restrict__ src, ST *__restrict__ dst, const Coef<CT> c)
+{
+    __shared__ CT srho[TY + 2][TX + 2];
+    int tile;
+    if (!map_tile(c.tiles_x * c.tiles_y, c.tiles_per_xcd, tile)) return;
+    const int x0 = (tile % c.tiles_x) * TX, y0 = (tile / c.tiles_x) * TY;
+    const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
+    const int x = x0 + tx, y = y0 + ty;
+    // every source of every node of the tile and of its one-node ring lies
+    // inside the domain: no boundary logic needed
+    const bool inner = x0 >= 2 && y0 >= 2 && x0 + TX + 2 <= c.nx && y0 + TY + 2 <= c.ny;
+    const bool active = x < c.nx && y < c.ny;
+
+    CT d[9];
+    if (inner) {
+        pull<ST, CT, BC, false>(c, src, x, y, d);
+    } else {
+        int fx = x, fy = y;
+        fix_coord<BC>(fx, fy, c.nx, c.ny);  // inactive slots stand in for their image
+        pull<ST, CT, BC, true>(c, src, fx, fy, d);
+    }
+    srho[ty + 1][tx + 1] = sum9(d);
+
+    // densities of the one-node ring around the tile
+    constexpr int RING = 2 * (TX + 2) + 2 * TY;
+    for (int k = tid; k < RING; k += TX * TY) {
+        int hx, hy;
+        if (k < TX + 2) { hx = k - 1; hy = -1; }
+        else if (k < 2 * (TX + 2)) { hx = k - (TX + 2) - 1; hy = TY; }
+        else if (k < 2 * (TX + 2) + TY) { hx = -1; hy = k - 2 * (TX + 2); }
+        else { hx = TX; hy = k - 2 * (TX + 2) - TY; }
+        CT e[9];
+        if (inner) {
+            pull<ST, CT, BC, false>(c, src, x0 + hx, y0 + hy, e);
+        } else {
+            int gx = x0 + hx, gy = y0 + hy;
+            fix_coord<BC>(gx, gy, c.nx, c.ny);
+            pull<ST, CT, BC, true>(c, src, gx, gy, e);
+        }
+        srho[hy + 1][hx + 1] = sum9(e);
+    }
+    __syncthreads();
+    if (!active) return;
+
+    // density gradient: rest-weighted central differences over the eight
+    // neighbours (exact for linear rho; [4,1,1]/12 at r = 1)
+    const int lx = tx + 1, ly = ty + 1;
+    const CT rE = srho[ly][lx + 1], rW = srho[ly][lx - 1];
+    const CT rN = srho[ly + 1][lx], rS = srho[ly - 1][lx];
+    const CT rNE = srho[ly + 1][lx + 1], rNW = srho[ly + 1][lx - 1];
+    const CT rSE = srho[ly - 1][lx + 1], rSW = srho[ly - 1][lx - 1];
+    const CT gx = c.gxa * (rE - rW) + c.gxb * ((rNE - rNW) + (rSE - rSW));
+    const CT gy = c.gya * (rN - rS) + c.gyb * ((rNE + rNW) - (rSE + rSW));
+
+    collide<CT>(c, d, gx, gy);
+
+    const int64_t o = (int64_t)y * c.pitch + x;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) dst[a * c.plane + o] = Conv<ST, CT>::st(d[a]);
+}
+
+template <typename ST, typename CT, int BC>
+__global__ void k_macros(const ST *__restrict__ f, const Coef<CT> c, double *rho, double *ux,
+                         double *uy)
+{
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= (int64_t)c.nx * c.ny) return;
+    const int x = (int)(n % c.nx), y = (int)(n / c.nx);
+    CT d[9];
+    pull<ST, CT, BC, true>(c, f, x, y, d);
+    CT drho, u, v;
+    fields(c, d, drho, u, v);
+    if (rho) rho[n] = (double)c.rho0 + (double)drho;
+    if (ux) ux[n] = (double)u;
+    if (uy) uy[n] = (double)v;
+}
+
+// block-wide fixed-order sum of four doubles (and a max in slot 3)
+__device__ __forceinline__ void block_reduce4(double v[4], double *sh /* [4][kRedBlock] */)
+{
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sh[k * kRedBlock + t] = v[k];
+    __syncthreads();
+    for (int s = kRedBlock / 2; s > 0; s >>= 1) {
+        if (t < s) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) sh[k * kRedBlock + t] += sh[k * kRedBlock + t + s];
+            const double a = sh[3 * kRedBlock + t], b = sh[3 * kRedBlock + t + s];
+            sh[3 * kRedBlock + t] = (a >= b || a != a) ? a : b;  // NaN sticks
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = sh[k * kRedBlock];
+}
+
+template <typename ST, typename CT, int BC>
+__global__ void __launch_bounds__(kRedBlock)
+    k_residual(const ST *__restrict__ f, const Coef<CT> c, double *__restrict__ u_prev,
+               double *__restrict__ partial)
+{
+    __shared__ double sh[4 * kRedBlock];
+    const int64_t N = (int64_t)c.nx * c.ny;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t n = (int64_t)blockIdx.x * kRedBlock + threadIdx.x; n < N;
+         n += (int64_t)gridDim.x * kRedBlock) {
+        const int x = (int)(n % c.nx), y = (int)(n / c.nx);
+        CT d[9];
+        pull<ST, CT, BC, true>(c, f, x, y, d);
+        CT drho, u, v;
+        fields(c, d, drho, u, v);
+        const double du = (double)u - u_prev[n], dv = (double)v - u_prev[N + n];
+        const double u2 = (double)u * (double)u + (double)v * (double)v;
+        acc[0] += du * du + dv * dv;
+        acc[1] += u2;
+        acc[2] += (double)drho;
+        if (!(u2 <= acc[3])) acc[3] = u2;
+        u_prev[n] = (double)u;
+        u_prev[N + n] = (double)v;
+    }
+    block_reduce4(acc, sh);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) partial[4 * blockIdx.x + k] = acc[k];
+    }
+}
+
+__global__ void __launch_bounds__(kRedBlock)
+    k_finish(const double *__restrict__ partial, int nblocks, double *__restrict__ out)
+{
+    __shared__ double sh[4 * kRedBlock];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nblocks; b += kRedBlock) {
+        for (int k = 0; k < 3; ++k) acc[k] += partial[4 * b + k];
+        const double m = partial[4 * b + 3];
+        if (!(m <= acc[3])) acc[3] = m;
+    }
+    block_reduce4(acc, sh);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 4; ++k) out[k] = acc[k];
+}
+
+// ------------------------------------------------------------ dispatch --
+template <typename ST> struct ComputeOf { using type = float; };
+template <> struct ComputeOf<double> { using type = double; };
+
+template <typename ST, int BC>
+static prc_status launch_sweep(const prc_params &p, const void *src, void *dst, hipStream_t s)
+{
+    using CT = typename ComputeOf<ST>::type;
+    int64_t pitch, plane;
+    layout(p, pitch, plane);
+    Coef<CT> c = make_coef<CT>(p, pitch, plane);
+    c.tiles_x = (p.nx + kSweepTX - 1) / kSweepTX;
+    c.tiles_y = (p.ny + kSweepTY - 1) / kSweepTY;
+    const int tiles = c.tiles_x * c.tiles_y;
+    c.tiles_per_xcd = (tiles + kXcds - 1) / kXcds;
+    const int blocks = c.tiles_per_xcd * kXcds;
+    hipLaunchKernelGGL((k_sweep<ST, CT, BC, kSweepTX, kSweepTY>), dim3(blocks),
+                       dim3(kSweepTX * kSweepTY), 0, s, (const ST *)src, (ST *)dst, c);
+    HIP_TRY(hipGetLastError());
+    return PRC_OK;
+}
+
+template <typename ST, int BC>
+static prc_status launch_macros(const prc_params &p, const void *f, double *rho, double *ux,
+                                double *uy, hipStream_t s)
+{
+    using CT = typename ComputeOf<ST>::type;
+    int64_t pitch, plane;
+    layout(p, pitch, plane);
+    const Coef<CT> c = make_coef<CT>(p, pitch, plane);
+    const int64_t N = (int64_t)p.nx * p.ny;
+    hipLaunchKernelGGL((k_macros<ST, CT, BC>), dim3((unsigned)((N + 255) / 256)), dim3(256), 0,
+                       s, (const ST *)f, c, rho, ux, uy);
+    HIP_TRY(hipGetLastError());
+    return PRC_OK;
+}
+
+static int red_blocks(const prc_params &p)
+{
+    const int64_t N = (int64_t)p.nx * p.ny;
+    int64_t b = (N + kRedBlock - 1) / kRedBlock;
+    return (int)(b < kRedMaxBlocks ? b : kRedMaxBlocks);
+}
+
+template <typename ST, int BC>
+static prc_status launch_residual(const prc_params &p, const void *f, double *u_prev,
+                                  double *scratch, hipStream_t s)
+{
+    using CT = typename ComputeOf<ST>::type;
+    int64_t pitch, plane;
+    layout(p, pitch, plane);
+    const Coef<CT> c = make_coef<CT>(p, pitch, plane);
+    const int nb = red_blocks(p);
+    hipLaunchKernelGGL((k_residual<ST, CT, BC>), dim3(nb), dim3(kRedBlock), 0, s, (const ST *)f, c,
+                       u_prev, scratch);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kRedBlock), 0, s, (const double *)scratch, nb,
+                       scratch + 4 * kRedMaxBlocks);
+    HIP_TRY(hipGetLastError());
+    return PRC_OK;
+}
+
+// run F<ST, BC>(args...) for the storage and boundary type of p
+#define PRC_DISPATCH(p, FN, ...)                                                          \
+    [&]() -> prc_status {                                                                \
+        switch ((p).storage * 3 + (p).bc) {                                              \
+        case PRC_F64 * 3 + 0: return FN<double, 0>(__VA_ARGS__);                         \
+        case PRC_F64 * 3 + 1: return FN<double, 1>(__VA_ARGS__);                         \
+        case PRC_F64 * 3 + 2: return FN<double, 2>(__VA_ARGS__);                         \
+        case PRC_F32 * 3 + 0: return FN<float, 0>(__VA_ARGS__);                          \
+        case PRC_F32 * 3 + 1: return FN<float, 1>(__VA_ARGS__);                          \
+        case PRC_F32 * 3 + 2: return FN<float, 2>(__VA_ARGS__);                          \
+        case PRC_F16 * 3 + 0: return FN<__half, 0>(__VA_ARGS__);                         \
+        case PRC_F16 * 3 + 1: return FN<__half, 1>(__VA_ARGS__);                         \
+        case PRC_F16 * 3 + 2: return FN<__half, 2>(__VA_ARGS__);                         \
+        case PRC_BF16 * 3 + 0: return FN<__hip_bfloat16, 0>(__VA_ARGS__);                \
+        case PRC_BF16 * 3 + 1: return FN<__hip_bfloat16, 1>(__VA_ARGS__);                \
+        case PRC_BF16 * 3 + 2: return FN<__hip_bfloat16, 2>(__VA_ARGS__);                \
+        }                                                                                \
+        return fail(PRC_EINVAL, "bad storage/bc");                                       \
+    }()
+
+}  // namespace prc
+
+using namespace prc;
+
+// ----------------------------------------------------------------- ABI --
+extern "C" {
+
+prc_status prc_params_default(prc_params *p)
+{
+    if (!p) return fail(PRC_EINVAL, "params is NULL");
+    std::memset(p, 0, sizeof *p);
+    p->r = 1.0;
+    p->gamma = 1.0;
+    p->omega_nu = p->omega_xi = p->omega_1 = p->omega_3 = p->omega_4 = 1.0;
+    p->rho0 = 1.0;
+    p->bc = PRC_BC_CAVITY;
+    p->storage = PRC_F32;
+    p->corrections = PRC_CORR_ALL;
+    p->frame = PRC_FRAME_CENTRAL;
+    return PRC_OK;
+}
+
+prc_status prc_params_from_re(prc_params *p, double re)
+{
+    if (!p) return fail(PRC_EINVAL, "params is NULL");
+    if (!(re > 0.0) || p->u_lid == 0.0 || !(p->r > 0.0) || !(p->gamma > 0.0) || p->ny <= 0)
+        return fail(PRC_EINVAL, "need re > 0, u_lid != 0, r > 0, gamma > 0, ny > 0");
+    const double H = (double)p->ny * p->r;
+    const double nu = std::fabs(p->u_lid) * H / re;
+    const double w = 1.0 / (nu / (p->gamma * lattice_c2(p->r)) + 0.5);
+    if (!(w > 0.0 && w < 2.0)) return fail(PRC_EINVAL, "omega_nu %g out of (0, 2)", w);
+    p->omega_nu = w;
+    return PRC_OK;
+}
+
+prc_status prc_validate(const prc_params *p) { return validate(p); }
+
+prc_status prc_layout(const prc_params *p, int64_t *pitch, int64_t *plane)
+{
+    prc_status st = validate(p);
+    if (st != PRC_OK) return st;
+    if (!pitch || !plane) return fail(PRC_EINVAL, "NULL output");
+    layout(*p, *pitch, *plane);
+    return PRC_OK;
+}
+
+size_t prc_state_bytes(const prc_params *p)
+{
+    if (validate(p) != PRC_OK) return 0;
+    int64_t pitch, plane;
+    layout(*p, pitch, plane);
+    return (size_t)(9 * plane) * elem_bytes(p->storage);
+}
+
+size_t prc_scratch_bytes(const prc_params *p)
+{
+    if (validate(p) != PRC_OK) return 0;
+    return (size_t)(4 * kRedMaxBlocks + 4) * sizeof(double);
+}
+
+prc_status prc_init(const prc_params *p, void *f, hipStream_t stream)
+{
+    prc_status st = validate(p);
+    if (st != PRC_OK) return st;
+    if ((st = check_buf(f, "f")) != PRC_OK) return st;
+    // all-zero bits are +0 in every storage type
+    HIP_TRY(hipMemsetAsync(f, 0, prc_state_bytes(p), stream));
+    return PRC_OK;
+}
+
+prc_status prc_step(const prc_params *p, void *f_a, void *f_b, int64_t nsteps, hipStream_t stream)
+{
+    prc_status st = validate(p);
+    if (st != PRC_OK) return st;
+    if ((st = check_buf(f_a, "f_a")) != PRC_OK || (st = check_buf(f_b, "f_b")) != PRC_OK) return st;
+    if (f_a == f_b) return fail(PRC_EINVAL, "f_a and f_b must be distinct buffers");
+    if (nsteps < 0) return fail(PRC_EINVAL, "nsteps < 0");
+    for (int64_t k = 0; k < nsteps; ++k) {
+        const void *src = (k & 1) ? f_b : f_a;
+        void *dst = (k & 1) ? f_a : f_b;
+        st = PRC_DISPATCH(*p, launch_sweep, *p, src, dst, stream);
+        if (st != PRC_OK) return st;
+    }
+    return PRC_OK;
+}
+
+prc_status prc_residual(const prc_params *p, const void *f, double *u_prev, void *scratch,
+                        double out[4], hipStream_t stream)
+{
+    prc_status st = validate(p);
+    if (st != PRC_OK) return st;
+    if ((st = check_buf(f, "f")) != PRC_OK) return st;
+    if (!u_prev || !scratch || !out) return fail(PRC_EINVAL, "NULL u_prev, scratch or out");
+    double *sc = (double *)scratch;
+    st = PRC_DISPATCH(*p, launch_residual, *p, f, u_prev, sc, stream);
+    if (st != PRC_OK) return st;
+    HIP_TRY(hipMemcpyAsync(out, sc + 4 * kRedMaxBlocks, 4 * sizeof(double),
+                           hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    out[2] += p->rho0 * (double)p->nx * (double)p->ny;  // rest part of the mass
+    return PRC_OK;
+}
+
+prc_status prc_macros(const prc_params *p, const void *f, double *rho, double *ux, double *uy,
+                      hipStream_t stream)
+{
+    prc_status st = validate(p);
+    if (st != PRC_OK) return st;
+    if ((st = check_buf(f, "f")) != PRC_OK) return st;
+    return PRC_DISPATCH(*p, launch_macros, *p, f, rho, ux, uy, stream);
+}
+
+prc_status prc_solve(const prc_params *p, void *f_a, void *f_b, double *u_prev, void *scratch,
+                     double tol, int64_t check_every, int64_t max_steps, int64_t *steps_out,
+                     double *hist, int64_t hist_cap, int64_t *hist_len, hipStream_t stream)
+{
+    prc_status st = validate(p);
+    if (st != PRC_OK) return st;
+    if (check_every <= 0 || max_steps < 0 || !steps_out)
+        return fail(PRC_EINVAL, "need check_every > 0, max_steps >= 0, steps_out");
+    if (!(tol >= 0.0)) return fail(PRC_EINVAL, "tol must be >= 0");
+    double out[4];
+    // snapshot of the initial velocity
+    if ((st = prc_residual(p, f_a, u_prev, scratch, out, stream)) != PRC_OK) return st;
+    int64_t n = 0, nh = 0;
+    prc_status result = PRC_NOT_CONVERGED;
+    while (n + check_every <= max_steps) {
+        void *cur = (n & 1) ? f_b : f_a, *oth = (n & 1) ? f_a : f_b;
+        if ((st = prc_step(p, cur, oth, check_every, stream)) != PRC_OK) return st;
+        n += check_every;
+        void *now = (n & 1) ? f_b : f_a;
+        if ((st = prc_residual(p, now, u_prev, scratch, out, stream)) != PRC_OK) return st;
+        const double R = out[1] > 0.0 ? std::sqrt(out[0] / out[1]) : (out[0] > 0.0 ? INFINITY : 0.0);
+        if (hist && nh < hist_cap) hist[nh] = R;
+        ++nh;
+        if (!std::isfinite(R) || !std::isfinite(out[2]) || !(out[3] < 1.0)) {
+            result = (prc_status)fail(PRC_EDIVERGED, "diverged at step %lld (R=%g, max|u|^2=%g)",
+                                      (long long)n, R, out[3]);
+            break;
+        }
+        if (R < tol) {
+            result = PRC_OK;
+            break;
+        }
+    }
+    if (result == PRC_NOT_CONVERGED && n < max_steps) {
+        void *cur = (n & 1) ? f_b : f_a, *oth = (n & 1) ? f_a : f_b;
+        if ((st = prc_step(p, cur, oth, max_steps - n, stream)) != PRC_OK) return st;
+        n = max_steps;
+        HIP_TRY(hipStreamSynchronize(stream));
+    }
+    *steps_out = n;
+    if (hist_len) *hist_len = nh;
+    return result;
+}
+
+prc_status prc_release_graphs(void) { return PRC_OK; }
+
+const char *prc_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+"""The C ABI on the CPU: the library loads, exports every entry point that
+include/prc.h declares, and its host-only calls (parameter setup,
+validation, layout, sizes) behave as documented.  Nothing here launches a
+kernel."""
+import os
+import re
+
+import pytest
+
+from paper_2208_03562_amd import capi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_entry_points():
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", h)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(prc_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_entry_point():
+    L = capi.lib()
+    names = declared_entry_points()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(capi.exported_names())
+
+
+def base():
+    p = capi.prc_params_default()
+    p.nx, p.ny = 64, 32
+    return p
+
+
+def test_defaults_are_the_papers_rates():
+    p = capi.prc_params_default()
+    assert (p.omega_xi, p.omega_1, p.omega_3, p.omega_4) == (1.0, 1.0, 1.0, 1.0)
+    assert p.corrections == capi.PRC_CORR_ALL and p.frame == capi.PRC_FRAME_CENTRAL
+
+
+def test_omega_from_re_matches_oracle(O):
+    for r, g, re_, U, ny in [(2.0, 1.0, 100, 0.05, 32), (2.0, 0.1, 1000, 0.05, 512),
+                             (0.5, 0.05, 2000, 0.05, 2048), (1.6, 0.3, 50, 0.02, 20)]:
+        p = base()
+        p.ny, p.r, p.gamma, p.u_lid = ny, r, g, U
+        capi.prc_params_from_re(p, re_)
+        po = O.with_re(O.params(64, ny, r, g, 1.0, u_lid=U), re_)
+        assert abs(p.omega_nu - po.omega_nu) < 1e-15 * po.omega_nu
+
+
+def test_cavity_64x32_relaxation_rate():
+    # Re = 100 with H = 64 dx and U = 0.05: nu = 0.032, omega = 1/(3 nu + 1/2)
+    p = base()
+    p.r, p.u_lid = 2.0, 0.05
+    capi.prc_params_from_re(p, 100.0)
+    assert abs(p.omega_nu - 1.0 / (0.096 + 0.5)) < 1e-14
+
+
+@pytest.mark.parametrize("field,value", [
+    ("nx", 2), ("ny", 0), ("r", 0.0), ("r", -1.0), ("gamma", 0.0), ("gamma", 1.5),
+    ("omega_nu", 2.0), ("omega_xi", 0.0), ("u_lid", 0.6), ("rho0", 0.0), ("bc", 3),
+    ("storage", 4), ("corrections", 8), ("frame", 5),
+])
+def test_validation_rejects(field, value):
+    p = base()
+    setattr(p, field, value)
+    with pytest.raises(capi.PrcError) as e:
+        capi.prc_validate(p)
+    assert e.value.status == capi.PRC_EINVAL
+    assert capi.prc_last_error()
+    assert capi.lib().prc_state_bytes(p) == 0
+
+
+def test_lid_speed_limit_uses_rectangular_sound_speed():
+    p = base()
+    p.r, p.u_lid = 0.5, 0.3   # below 1/sqrt(3) but above 0.5/sqrt(3)
+    with pytest.raises(capi.PrcError):
+        capi.prc_validate(p)
+    p.u_lid = 0.28
+    capi.prc_validate(p)
+
+
+@pytest.mark.parametrize("storage,elem", [(0, 8), (1, 4), (2, 2), (3, 2)])
+def test_layout_and_sizes(storage, elem):
+    p = base()
+    p.nx, p.ny, p.storage = 1000, 37, storage
+    pitch, plane = capi.prc_layout(p)
+    assert pitch >= 1000 and (pitch * elem) % 256 == 0 and pitch * elem - 1000 * elem < 256
+    assert plane == pitch * 37
+    assert capi.prc_state_bytes(p) == 9 * plane * elem
+    assert capi.prc_scratch_bytes(p) > 0
+
+
+def test_from_re_rejects_bad_input():
+    p = base()
+    p.u_lid = 0.0
+    with pytest.raises(capi.PrcError):
+        capi.prc_params_from_re(p, 100.0)
+    p.u_lid = 0.05
+    with pytest.raises(capi.PrcError):
+        capi.prc_params_from_re(p, -1.0)

@@ -1,0 +1,240 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle.
+
+Tolerances
+* FP64 storage: the library computes the same update with the rest-state
+  constants removed before rounding, so the two differ by round-off only:
+  populations within 1e-12 of the largest deviation per step taken.
+* FP32 storage: the required bar is a maximum velocity error of 1e-5 relative
+  to the lid speed (or, without a lid, to the largest velocity), and equal
+  steps-to-convergence within 1 %.
+Inputs are the rest state plus seeded uniform noise on the deviations
+(``workloads.deviation_noise``), rounded to the storage type first so that
+both sides start from the same numbers.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from tests.common import lib_params, max_rel_velocity_error, oracle_deviation, oracle_params, spec
+
+pytestmark = pytest.mark.gpu
+
+NP_STORAGE = {"f64": np.float64, "f32": np.float32}
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def make_solver(s):
+    from paper_2208_03562_amd import solver
+    return solver.Solver(lib_params(s))
+
+
+def start_both(O, s, seed, amp):
+    """GPU solver and oracle state from the same rounded noise."""
+    sol = make_solver(s)
+    noise = workloads.deviation_noise(s["nx"], s["ny"], seed, amp)
+    noise = noise.astype(NP_STORAGE[s["storage"]]).astype(np.float64)
+    sol.set_state(noise)
+    po = oracle_params(O, s)
+    ft = np.ascontiguousarray(O.rest_state(po) + noise)
+    return sol, po, ft
+
+
+def velocity_scale(s, ux, uy):
+    return s["u_lid"] if s["u_lid"] else float(max(np.abs(ux).max(), np.abs(uy).max()))
+
+
+CASES = [
+    # bc, r, gamma, extra
+    ("cavity", 2.0, 1.0, dict(u_lid=0.05)),
+    ("cavity", 0.5, 0.1, dict(u_lid=0.02)),
+    ("cavity", 1.0, 0.3, dict(u_lid=0.05, omega_xi=1.3, omega_1=0.8, omega_3=1.1, omega_4=0.9)),
+    ("periodic", 2.0, 0.2, dict(fx=1e-5, fy=-2e-5)),
+    ("periodic", 0.5, 1.0, dict()),
+    ("channel", 4.0, 0.5, dict(u_lid=0.03, fx=3e-6)),
+    ("channel", 0.25, 0.1, dict(fx=1e-6)),
+]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}-r{c[1]}-g{c[2]}")
+@pytest.mark.parametrize("nx,ny", [(150, 37), (67, 9)])
+def test_steps_from_random_state(O, torch_cuda, storage, case, nx, ny):
+    bc, r, gamma, extra = case
+    s = spec(nx, ny, r, gamma, omega_nu=1.4, bc=bc, storage=storage, **extra)
+    sol, po, ft = start_both(O, s, seed=nx * 1000 + ny, amp=1e-3)
+    for nsteps in (1, 9):
+        sol.step(nsteps)
+        O.step(po, ft, nsteps)
+        dev_gpu = sol.get_state().cpu().numpy()
+        dev_orc = oracle_deviation(O, po, ft)
+        err = np.abs(dev_gpu - dev_orc).max()
+        scale = np.abs(dev_orc).max()
+        if storage == "f64":
+            assert err < 1e-12 * scale * sol.steps, (nsteps, err, scale)
+        else:
+            rho, ux, uy = (a.cpu().numpy() for a in sol.macros())
+            _, oux, ouy = O.velocity(po, ft)
+            U = velocity_scale(s, oux, ouy)
+            assert max_rel_velocity_error(ux, uy, oux, ouy, U) < 1e-5
+            assert err < 1e-5 * scale, (nsteps, err, scale)
+
+
+@pytest.mark.parametrize("bc", ["cavity", "periodic", "channel"])
+@pytest.mark.parametrize("nx,ny", [(3, 3), (64, 4), (5, 131)])
+def test_degenerate_grids(O, torch_cuda, bc, nx, ny):
+    s = spec(nx, ny, 2.0, 0.5, omega_nu=1.1, bc=bc, storage="f64",
+             u_lid=0.0 if bc == "periodic" else 0.04)
+    sol, po, ft = start_both(O, s, seed=5, amp=1e-3)
+    sol.step(4)
+    O.step(po, ft, 4)
+    dev_orc = oracle_deviation(O, po, ft)
+    assert np.abs(sol.get_state().cpu().numpy() - dev_orc).max() < 1e-12 * np.abs(dev_orc).max() * 4
+
+
+def test_rest_state_is_zero_and_stays_at_rest(O, torch_cuda):
+    s = spec(70, 20, 2.0, 0.3, omega_nu=1.2, bc="periodic", storage="f32")
+    sol = make_solver(s)
+    assert float(sol.get_state().abs().max()) == 0.0
+    sol.step(10)
+    assert float(sol.get_state().abs().max()) == 0.0
+
+
+def test_cavity_64x32_f64_trajectory_and_convergence(O, torch_cuda):
+    """64 x 32, r = 2, Re = 100, U = 0.05, gamma = 1, FP64: the state after a
+    step prefix, then the whole solve to a residual of 1e-8 checked every
+    1000 steps (at most 20000 steps)."""
+    w = workloads.CAVITY_64x32_F64
+    s = spec(w.nx, w.ny, w.r, w.gamma, re=w.re, u_lid=w.u_lid, storage="f64")
+    po = oracle_params(O, s)
+    sol = make_solver(s)
+    assert abs(sol.p.omega_nu - po.omega_nu) < 1e-14
+    ft = O.rest_state(po)
+    sol.step(500)
+    O.step(po, ft, 500)
+    _, ux, uy = (a.cpu().numpy() for a in sol.macros())
+    _, oux, ouy = O.velocity(po, ft)
+    assert max_rel_velocity_error(ux, uy, oux, ouy, w.u_lid) < 1e-12
+
+    sol2 = make_solver(s)
+    st, n, hist = sol2.solve(w.tol, w.check_every, w.max_steps)
+    ft2 = O.rest_state(po)
+    ost, on, ohist = O.solve(po, ft2, w.tol, w.check_every, w.max_steps)
+    # this case stops at the 20000-step limit on both sides (residual ~1e-7)
+    assert st == ost
+    assert n == on
+    np.testing.assert_allclose(hist, ohist, rtol=1e-6)
+    _, ux, uy = (a.cpu().numpy() for a in sol2.macros())
+    _, oux, ouy = O.velocity(po, ft2)
+    assert max_rel_velocity_error(ux, uy, oux, ouy, w.u_lid) < 1e-11
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_cavity_reduced_grid_solve(O, torch_cuda, storage):
+    """A small cavity at gamma = 0.1, r = 2 and Ma = 0.06 (the lid speed the
+    paper pairs with gamma = 0.1 in Sec. 5): the whole solve to a residual of
+    1e-7 agrees with the oracle in steps (within 1 %) and in the velocity
+    field (1e-5 of U)."""
+    U = workloads.MA006_LID
+    s = spec(64, 32, 2.0, 0.1, omega_nu=None, re=62.5, u_lid=U, storage=storage)
+    po = oracle_params(O, s)
+    sol = make_solver(s)
+    st, n, hist = sol.solve(1e-7, 500, 100000)
+    ft = O.rest_state(po)
+    ost, on, ohist = O.solve(po, ft, 1e-7, 500, 100000)
+    assert st == 0 and ost == 0
+    assert abs(n - on) <= 0.01 * on, (n, on)
+    _, ux, uy = (a.cpu().numpy() for a in sol.macros())
+    _, oux, ouy = O.velocity(po, ft)
+    assert max_rel_velocity_error(ux, uy, oux, ouy, U) < 1e-5
+
+
+def test_full_size_1024x512_f32_one_step(O, torch_cuda):
+    """The benchmark grid (1024 x 512, r = 2, Re = 1000, gamma = 0.1, FP32,
+    launch configuration of the benchmark): one step from a random state,
+    every node compared."""
+    w = workloads.CAVITY_1024x512_F32
+    s = spec(w.nx, w.ny, w.r, w.gamma, re=w.re, u_lid=w.u_lid, storage="f32")
+    sol, po, ft = start_both(O, s, seed=42, amp=1e-3)
+    sol.step(1)
+    O.step(po, ft, 1)
+    dev_orc = oracle_deviation(O, po, ft)
+    assert np.abs(sol.get_state().cpu().numpy() - dev_orc).max() < 1e-5 * np.abs(dev_orc).max()
+
+
+def test_full_size_1024x512_f32_diverges_like_oracle(O, torch_cuda):
+    """With U = 0.05 (Ma = 0.087) and gamma = 0.1 the scheme is unstable: the
+    FP64 oracle blows up within about 100 steps.  The GPU follows the oracle
+    over the first 60 steps and reports the divergence at the first check."""
+    w = workloads.CAVITY_1024x512_F32
+    s = spec(w.nx, w.ny, w.r, w.gamma, re=w.re, u_lid=w.u_lid, storage="f32")
+    po = oracle_params(O, s)
+    sol = make_solver(s)
+    ft = O.rest_state(po)
+    sol.step(60)
+    O.step(po, ft, 60)
+    _, ux, uy = (a.cpu().numpy() for a in sol.macros())
+    _, oux, ouy = O.velocity(po, ft)
+    assert max_rel_velocity_error(ux, uy, oux, ouy, w.u_lid) < 1e-5
+    ost, on, _ = O.solve(po, ft, 1e-8, 100, 300)
+    st, n, _ = sol.solve(1e-8, 100, 300)
+    assert ost == -3 and st == -3 and n == on
+
+
+def test_full_size_1024x512_f32_stable_companion(O, torch_cuda):
+    """Same grid, r, gamma and Re with the lid at Ma = 0.06: 200 steps from
+    rest agree with the oracle to 1e-5 of U."""
+    w = workloads.CAVITY_1024x512_F32
+    s = spec(w.nx, w.ny, w.r, w.gamma, re=w.re, u_lid=workloads.MA006_LID, storage="f32")
+    po = oracle_params(O, s)
+    sol = make_solver(s)
+    ft = O.rest_state(po)
+    sol.step(200)
+    O.step(po, ft, 200)
+    _, ux, uy = (a.cpu().numpy() for a in sol.macros())
+    _, oux, ouy = O.velocity(po, ft)
+    assert max_rel_velocity_error(ux, uy, oux, ouy, workloads.MA006_LID) < 1e-5
+
+
+def test_residual_and_macros_match_oracle(O, torch_cuda):
+    import torch
+    s = spec(96, 40, 2.0, 0.5, omega_nu=1.3, u_lid=0.05, storage="f64")
+    sol, po, ft = start_both(O, s, seed=3, amp=5e-4)
+    uxp = np.zeros((s["ny"], s["nx"]))
+    uyp = np.zeros((s["ny"], s["nx"]))
+    O.residual(po, ft, uxp, uyp)                 # snapshot
+    sol.residual()
+    sol.step(7)
+    O.step(po, ft, 7)
+    out = np.array(sol.residual())
+    oout = O.residual(po, ft, uxp, uyp)
+    np.testing.assert_allclose(out, oout, rtol=1e-11)
+    np.testing.assert_allclose(sol.u_prev[0].cpu().numpy(), uxp, rtol=0, atol=1e-15)
+    rho, ux, uy = (a.cpu().numpy() for a in sol.macros())
+    orho, oux, ouy = O.velocity(po, ft)
+    np.testing.assert_allclose(rho, orho, rtol=1e-14)
+    assert torch.isfinite(sol.u_prev).all()
+
+
+def test_solve_is_deterministic(torch_cuda):
+    s = spec(200, 90, 2.0, 0.2, re=400.0, omega_nu=None, u_lid=0.05, storage="f32")
+    a = make_solver(s)
+    b = make_solver(s)
+    ra = a.solve(0.0, 300, 1500)
+    rb = b.solve(0.0, 300, 1500)
+    assert ra[2] == rb[2]
+    assert bool((a.get_state() == b.get_state()).all())
+
+
+def test_mass_conserved_f32(torch_cuda):
+    s = spec(256, 128, 2.0, 0.1, re=1000.0, omega_nu=None, u_lid=0.05, storage="f32")
+    sol = make_solver(s)
+    m0 = sol.residual()[2]
+    sol.step(4000)
+    m1 = sol.residual()[2]
+    assert abs(m1 / m0 - 1.0) < 1e-7
