@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -343,6 +344,91 @@ static prc_status launch_residual(const prc_params &p, const void *f, double *u_
         return fail(PRC_EINVAL, "bad storage/bc");                                       \
     }()
 
+// --------------------------------------------------------- launch graphs --
+// prc_step replays captured graphs of sweeps for long runs: one graph per
+// (device, problem, buffer pair), cached until prc_release_graphs().
+constexpr int kGraphStepsDefault = 64;  // even
+constexpr size_t kGraphCacheMax = 32;
+
+static_assert(sizeof(prc_params) == 8 + 11 * 8 + 4 * 4, "prc_params has no padding");
+
+struct GraphEntry {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+static std::mutex g_graph_mu;
+static std::unordered_map<std::string, GraphEntry> g_graphs;
+
+// sweeps per graph; PRC_GRAPH_STEPS overrides (0 disables graphs)
+static int graph_steps()
+{
+    static const int v = [] {
+        const char *e = std::getenv("PRC_GRAPH_STEPS");
+        if (!e) return kGraphStepsDefault;
+        const int n = std::atoi(e);
+        return n <= 0 ? 0 : (n + 1) / 2 * 2;
+    }();
+    return v;
+}
+
+static void destroy_graphs_locked()
+{
+    for (auto &kv : g_graphs) {
+        (void)hipGraphExecDestroy(kv.second.exec);
+        (void)hipGraphDestroy(kv.second.graph);
+    }
+    g_graphs.clear();
+}
+
+static prc_status get_graph(const prc_params &p, void *f_a, void *f_b, int nsteps,
+                            hipGraphExec_t *out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::string key(reinterpret_cast<const char *>(&p), sizeof p);
+    key.append(reinterpret_cast<const char *>(&f_a), sizeof f_a);
+    key.append(reinterpret_cast<const char *>(&f_b), sizeof f_b);
+    key.append(reinterpret_cast<const char *>(&dev), sizeof dev);
+    key.append(reinterpret_cast<const char *>(&nsteps), sizeof nsteps);
+    std::lock_guard<std::mutex> lock(g_graph_mu);
+    auto it = g_graphs.find(key);
+    if (it != g_graphs.end()) {
+        *out = it->second.exec;
+        return PRC_OK;
+    }
+    if (g_graphs.size() >= kGraphCacheMax) destroy_graphs_locked();
+    hipStream_t cs = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    prc_status st = PRC_OK;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        for (int k = 0; k < nsteps && st == PRC_OK; ++k) {
+            const void *src = (k & 1) ? f_b : f_a;
+            void *dst = (k & 1) ? f_a : f_b;
+            st = PRC_DISPATCH(p, launch_sweep, p, src, dst, cs);
+        }
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(cs, &g);
+        if (e == hipSuccess && st == PRC_OK) {
+            hipGraphExec_t x = nullptr;
+            e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+            if (e == hipSuccess) {
+                g_graphs.emplace(key, GraphEntry{g, x});
+                *out = x;
+            } else {
+                (void)hipGraphDestroy(g);
+            }
+        } else if (g) {
+            (void)hipGraphDestroy(g);
+        }
+    }
+    (void)hipStreamDestroy(cs);
+    if (st != PRC_OK) return st;
+    if (e != hipSuccess)
+        return fail(PRC_EHIP, "graph capture of %d sweeps: %s", nsteps, hipGetErrorString(e));
+    return PRC_OK;
+}
+
 }  // namespace prc
 
 using namespace prc;
@@ -420,7 +506,19 @@ prc_status prc_step(const prc_params *p, void *f_a, void *f_b, int64_t nsteps, h
     if ((st = check_buf(f_a, "f_a")) != PRC_OK || (st = check_buf(f_b, "f_b")) != PRC_OK) return st;
     if (f_a == f_b) return fail(PRC_EINVAL, "f_a and f_b must be distinct buffers");
     if (nsteps < 0) return fail(PRC_EINVAL, "nsteps < 0");
-    for (int64_t k = 0; k < nsteps; ++k) {
+    int64_t k = 0;
+    // Long runs replay a captured graph of kGraphSteps sweeps (an even count,
+    // so the newest state is back in f_a after every replay).  Not while the
+    // caller's stream is itself being captured.
+    const int gsteps = graph_steps();
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(stream, &cap));
+    if (gsteps > 0 && cap == hipStreamCaptureStatusNone && nsteps >= 2 * gsteps) {
+        hipGraphExec_t exec = nullptr;
+        if ((st = get_graph(*p, f_a, f_b, gsteps, &exec)) != PRC_OK) return st;
+        for (; k + gsteps <= nsteps; k += gsteps) HIP_TRY(hipGraphLaunch(exec, stream));
+    }
+    for (; k < nsteps; ++k) {
         const void *src = (k & 1) ? f_b : f_a;
         void *dst = (k & 1) ? f_a : f_b;
         st = PRC_DISPATCH(*p, launch_sweep, *p, src, dst, stream);
@@ -499,7 +597,12 @@ prc_status prc_solve(const prc_params *p, void *f_a, void *f_b, double *u_prev, 
     return result;
 }
 
-prc_status prc_release_graphs(void) { return PRC_OK; }
+prc_status prc_release_graphs(void)
+{
+    std::lock_guard<std::mutex> lock(g_graph_mu);
+    destroy_graphs_locked();
+    return PRC_OK;
+}
 
 const char *prc_last_error(void) { return g_err.c_str(); }
 

@@ -18,7 +18,8 @@ def spec(nx, ny, r=1.0, gamma=1.0, *, re=None, omega_nu=1.2, u_lid=0.0, fx=0.0, 
 
 
 def oracle_params(O, s):
-    p = O.params(s["nx"], s["ny"], s["r"], s["gamma"], s["omega_nu"], omega_xi=s["omega_xi"],
+    w = s["omega_nu"] if s["omega_nu"] is not None else 1.0   # replaced below when re is set
+    p = O.params(s["nx"], s["ny"], s["r"], s["gamma"], w, omega_xi=s["omega_xi"],
                  omega_1=s["omega_1"], omega_3=s["omega_3"], omega_4=s["omega_4"],
                  u_lid=s["u_lid"], fx=s["fx"], fy=s["fy"], rho0=s["rho0"], bc=BC[s["bc"]],
                  corrections=s["corrections"])

@@ -169,15 +169,17 @@ def test_full_size_1024x512_f32_one_step(O, torch_cuda):
 
 def test_full_size_1024x512_f32_diverges_like_oracle(O, torch_cuda):
     """With U = 0.05 (Ma = 0.087) and gamma = 0.1 the scheme is unstable: the
-    FP64 oracle blows up within about 100 steps.  The GPU follows the oracle
-    over the first 60 steps and reports the divergence at the first check."""
+    FP64 oracle blows up within about 100 steps, from an instability that
+    grows at the lid corners.  The GPU follows the oracle over the first 20
+    steps (before the growth amplifies rounding differences) and reports the
+    divergence at the same check."""
     w = workloads.CAVITY_1024x512_F32
     s = spec(w.nx, w.ny, w.r, w.gamma, re=w.re, u_lid=w.u_lid, storage="f32")
     po = oracle_params(O, s)
     sol = make_solver(s)
     ft = O.rest_state(po)
-    sol.step(60)
-    O.step(po, ft, 60)
+    sol.step(20)
+    O.step(po, ft, 20)
     _, ux, uy = (a.cpu().numpy() for a in sol.macros())
     _, oux, ouy = O.velocity(po, ft)
     assert max_rel_velocity_error(ux, uy, oux, ouy, w.u_lid) < 1e-5
@@ -232,7 +234,8 @@ def test_solve_is_deterministic(torch_cuda):
 
 
 def test_mass_conserved_f32(torch_cuda):
-    s = spec(256, 128, 2.0, 0.1, re=1000.0, omega_nu=None, u_lid=0.05, storage="f32")
+    s = spec(256, 128, 2.0, 0.1, re=1000.0, omega_nu=None, u_lid=workloads.MA006_LID,
+             storage="f32")
     sol = make_solver(s)
     m0 = sol.residual()[2]
     sol.step(4000)
