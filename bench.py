@@ -116,8 +116,34 @@ def run_cpu_baseline(w: workloads.Cavity, budget_s: float):
                        f"(after 1 untimed step), OpenMP over rows")
 
 
+def pmc_run(steps: int):
+    """Short fixed workload for hardware-counter runs: a plain device copy of
+    256 MiB each way (the reference for scaling byte counters), then `steps`
+    sweeps of the 1024x512 and of the 4096x2048 FP32 cavity."""
+    import torch
+    from paper_2208_03562_amd import solver
+
+    n = 256 * 2 ** 20 // 4
+    a = torch.ones(n, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"[pmc] 5 copies of {4 * n} bytes done")
+    for w in (workloads.CAVITY_1024x512_F32, workloads.CAVITY_4096x2048_F32):
+        p = solver.make_params(w.nx, w.ny, w.r, w.gamma, re=w.re, u_lid=w.u_lid,
+                               storage=STORAGE[w.storage])
+        sol = solver.Solver(p, device="cuda:0")
+        sol.step(steps)
+        torch.cuda.synchronize()
+        log(f"[pmc] {steps} sweeps of {w.name} done")
+        del sol
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--pmc-run", type=int, default=0,
+                    help="only run the short counter workload with this many sweeps per grid")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=2000)
@@ -134,6 +160,9 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.pmc_run > 0:
+        pmc_run(args.pmc_run)
+        return
 
     w = workloads.CAVITY_1024x512_F32
     main_res = run_gpu(w, args.steps, args.warmup)

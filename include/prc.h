@@ -27,7 +27,9 @@
  * population a in the velocity order of Sec. 2 eq. 3a/3b
  * (0 rest, 1 E, 2 N, 3 W, 4 S, 5 NE, 6 NW, 7 SW, 8 SE).  Element (a, j, i)
  * -- node i along x in [0, nx), row j along y in [0, ny) -- sits at element
- * offset a * plane + j * pitch + i, with pitch and plane from prc_layout().
+ * offset a * plane_stride + j * row_stride + i, with both strides from
+ * prc_layout(); rows are padded to 256 bytes.  Elements not addressed by any
+ * (a, j, i) are padding that the kernels never read.
  * The stored value is the DEVIATION f_a - rho0 * w_a of the post-collision
  * population from the rest state (w_a: product of the one-dimensional rest
  * weights of variance c_s^2 along x and c_s^2 / r^2 along y, c_s^2 = q^2/3,
@@ -115,11 +117,12 @@ prc_status prc_params_from_re(prc_params *p, double re);
 /* Check *p against the rules above without touching the GPU. Host only. */
 prc_status prc_validate(const prc_params *p);
 
-/* Element pitch of one row and element stride of one plane of the population
- * state (see the layout above).  Host only. */
-prc_status prc_layout(const prc_params *p, int64_t *pitch, int64_t *plane);
+/* Element strides of the population state (see the layout above): from one
+ * row to the next and from one population plane to the next.  Host only. */
+prc_status prc_layout(const prc_params *p, int64_t *row_stride, int64_t *plane_stride);
 
-/* Bytes of one population state buffer (9 planes); 0 if *p is invalid. */
+/* Bytes of one population state buffer (at most 4 GiB: larger grids are
+ * rejected by validation); 0 if *p is invalid. */
 size_t prc_state_bytes(const prc_params *p);
 
 /* Bytes of the scratch buffer that prc_residual and prc_solve need. */
@@ -169,6 +172,24 @@ prc_status prc_solve(const prc_params *p, void *f_a, void *f_b, double *u_prev,
                      void *scratch, double tol, int64_t check_every,
                      int64_t max_steps, int64_t *steps_out, double *hist,
                      int64_t hist_cap, int64_t *hist_len, hipStream_t stream);
+
+/* Autotuner: time every tile shape of the sweep kernel (threads along x by
+ * along y: 0 = 64 x 4, 1 = 64 x 8, 2 = 128 x 4) for this problem's storage,
+ * boundaries and grid size, on two scratch state buffers that the call
+ * allocates and frees itself (hipMalloc/hipFree), and use the fastest for
+ * every later sweep of a problem with the same storage, boundaries and grid
+ * size in this process.  The tile shape changes only the speed, not the
+ * results.  tile_out (host, may be NULL) receives the chosen index.  Without
+ * a tuning call the library picks 128 x 4 for grids at least 256 nodes wide
+ * and 64 x 4 otherwise.  Synchronises the stream; PRC_EHIP if the scratch
+ * allocation fails. */
+prc_status prc_tune(const prc_params *p, int32_t *tile_out, hipStream_t stream);
+
+/* Use tile shape `tile` (index as for prc_tune; -1 forgets any choice) for
+ * problems with this storage, boundaries and grid size.  Host only; does not
+ * touch the GPU.  Launch graphs already cached by prc_step keep the shape
+ * they were captured with until prc_release_graphs. */
+prc_status prc_set_tile(const prc_params *p, int32_t tile);
 
 /* Drop the launch graphs cached by prc_step (they hold no user memory). */
 prc_status prc_release_graphs(void);

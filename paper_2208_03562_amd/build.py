@@ -9,7 +9,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libprc.so")
 SOURCES = [os.path.join(CSRC, "prc_lib.hip")]
-HEADERS = [os.path.join(CSRC, h) for h in ("prc_coef.hpp", "prc_device.hpp")] + [
+HEADERS = [os.path.join(CSRC, h) for h in ("prc_coef.hpp", "prc_device.hpp", "prc_collide.hpp",
+                                         "prc_sweep.hpp")] + [
     os.path.join(ROOT, "include", "prc.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -75,6 +75,8 @@ _PROTOS = {
     "prc_solve": (ctypes.c_int, [_P, _VP, _VP, _DP, _VP, ctypes.c_double, ctypes.c_int64,
                                  ctypes.c_int64, _I64P, ctypes.POINTER(ctypes.c_double),
                                  ctypes.c_int64, _I64P, _VP]),
+    "prc_tune": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), _VP]),
+    "prc_set_tile": (ctypes.c_int, [_P, ctypes.c_int32]),
     "prc_release_graphs": (ctypes.c_int, []),
     "prc_last_error": (ctypes.c_char_p, []),
 }
@@ -130,10 +132,11 @@ def prc_validate(p: prc_params) -> None:
 
 
 def prc_layout(p: prc_params):
-    pitch, plane = ctypes.c_int64(), ctypes.c_int64()
-    _check("prc_layout", lib().prc_layout(ctypes.byref(p), ctypes.byref(pitch),
+    """(row_stride, plane_stride) in elements."""
+    row, plane = ctypes.c_int64(), ctypes.c_int64()
+    _check("prc_layout", lib().prc_layout(ctypes.byref(p), ctypes.byref(row),
                                           ctypes.byref(plane)))
-    return pitch.value, plane.value
+    return row.value, plane.value
 
 
 def prc_state_bytes(p: prc_params) -> int:
@@ -188,3 +191,14 @@ def prc_release_graphs() -> None:
 
 def prc_last_error() -> str:
     return last_error()
+
+
+def prc_tune(p: prc_params, stream: int = 0) -> int:
+    """Time the sweep's tile shapes for this problem; returns the chosen index."""
+    t = ctypes.c_int32(-1)
+    _check("prc_tune", lib().prc_tune(ctypes.byref(p), ctypes.byref(t), stream))
+    return t.value
+
+
+def prc_set_tile(p: prc_params, tile: int) -> None:
+    _check("prc_set_tile", lib().prc_set_tile(ctypes.byref(p), int(tile)))

@@ -2,10 +2,12 @@
 //
 // Every constant is computed once in double precision from prc_params and
 // handed to the kernels by value in the arithmetic type of the storage
-// (double for PRC_F64, float otherwise).  Names follow the appendix of
-// arXiv 2208.03562: P_gamma, Q_gamma, U_gamma, the strain-solve coefficients
-// of eq. 46, the correction coefficients of eq. 38-40 and the transport
-// relation nu = gamma c_s^2 (1/omega_nu - 1/2).
+// (double for PRC_F64, float otherwise).  Products of constants are formed
+// here, not per node (gfx950 has no scalar floating-point unit, so a product
+// of two kernel arguments would cost a vector instruction in every thread).
+// Names follow the appendix of arXiv 2208.03562: P_gamma, Q_gamma, U_gamma,
+// the strain-solve coefficients of eq. 46, the correction coefficients of
+// eq. 38-40 and the transport relation nu = gamma c_s^2 (1/omega_nu - 1/2).
 #pragma once
 
 #include <cmath>
@@ -21,23 +23,30 @@ constexpr int kXcds = 8;
 template <typename CT>
 struct Coef {
     int32_t nx, ny;
-    int64_t pitch, plane;
-    int32_t corr;
+    int32_t pitch;          // elements from one row to the next (same plane)
+    uint32_t row_bytes;     // pitch * element size
+    uint32_t plane_bytes;   // bytes from one population plane to the next
+    uint32_t state_bytes;   // bytes of the whole state
+    int32_t corr;           // correction bitmask (generic kernels only)
     int32_t tiles_x, tiles_y, tiles_per_xcd;  // sweep tile grid (set per launch)
-    CT r, r2, inv_r, inv_r2;
-    CT rho0, c2, c2rho0;
-    CT ig1;        // 1/gamma - 1
-    CT Pg, Qg;     // 4/gamma^2 - 1/gamma, 1/gamma^2 - 1/gamma
-    CT g3;         // 1/gamma^2 - 3/gamma + 2 (third-order equilibria, eq. 14)
-    CT Ab, Bb;     // (U_gamma c2 - 1)/2, (U_gamma c2 - r^2)/2 (eq. 43)
-    CT a1, a2;     // 3 c2 - 1, 3 c2 - r^2 (anisotropy factors)
-    CT cb0, cs0;   // -2 c2 / omega_xi, 2 c2 / omega_nu (eq. 46)
+    CT r, r2;               // y lattice speed and its square (scaling S)
+    CT hinv_r, hinv_r2;     // 1/(2r), 1/(2r^2) (S^-1 with the halves of P^-1)
+    CT rho0, c2, c2x2, c2sq, c2rho0;  // c2 = c_s^2; 2 c2; c2^2; c2 rho0
+    CT ig1;                 // 1/gamma - 1
+    CT Pg, Qg;              // 4/gamma^2 - 1/gamma, 1/gamma^2 - 1/gamma
+    CT g3;                  // 1/gamma^2 - 3/gamma + 2 (third-order equilibria, eq. 14)
+    CT Ab, Bb;              // (U_gamma c2 - 1)/2, (U_gamma c2 - r^2)/2 (eq. 43)
+    CT a1, a2;              // 3 c2 - 1, 3 c2 - r^2 (anisotropy factors)
+    CT cb0, cs0;            // -2 c2 / omega_xi, 2 c2 / omega_nu (eq. 46)
+    CT mhxi, mhnu;          // -(1/omega_xi - 1/2), -(1/omega_nu - 1/2)
+    CT mhxi2, mhnu2;        // twice those (density-gradient terms)
+    CT kq11, kl11;          // k11 corrections: -Q_gamma h_nu, -(1/gamma - 1) h_nu c2
     CT om_nu, om_xi, om_3, om_4;
-    CT hnu, hxi;   // 1/omega - 1/2
-    CT fxh, fyh;   // F / (2 gamma) (eq. hydrodynamicfields)
-    CT qfx, qfy;   // Q_gamma F (central source moments, eq. 13-central)
-    CT sxi, snu;   // 1 - omega_xi/2, 1 - omega_nu/2
-    CT lid;        // rho0 U c2 / (2 r^2): wall momentum term of a diagonal link
+    CT fxh, fyh;            // F / (2 gamma) (eq. hydrodynamicfields)
+    CT fxg, fyg;            // F / gamma: change of the first-order central moments
+    CT qfx, qfy;            // Q_gamma F (central source moments, eq. 13-central)
+    CT sxi2, snu2, snu;     // 2 (1 - omega_xi/2), 2 (1 - omega_nu/2), 1 - omega_nu/2
+    CT lid;                 // rho0 U c2 / (2 r^2): wall momentum term of a diagonal link
     CT gxa, gxb, gya, gyb;  // density-gradient stencil weights
 };
 
@@ -48,26 +57,33 @@ inline double lattice_c2(double r)
 }
 
 template <typename CT>
-inline Coef<CT> make_coef(const prc_params &p, int64_t pitch, int64_t plane)
+inline Coef<CT> make_coef(const prc_params &p, int64_t row_stride, int64_t plane_stride,
+                          int64_t total, int64_t elem)
 {
     const double r = p.r, g = p.gamma, c2 = lattice_c2(r);
     const double Ug = 2.0 / g + 1.0;
+    const double Qg = 1.0 / (g * g) - 1.0 / g;
+    const double hnu = 1.0 / p.omega_nu - 0.5, hxi = 1.0 / p.omega_xi - 0.5;
     Coef<CT> c{};
     c.nx = p.nx;
     c.ny = p.ny;
-    c.pitch = pitch;
-    c.plane = plane;
+    c.pitch = (int32_t)row_stride;
+    c.row_bytes = (uint32_t)(row_stride * elem);
+    c.plane_bytes = (uint32_t)(plane_stride * elem);
+    c.state_bytes = (uint32_t)(total * elem);
     c.corr = p.corrections;
     c.r = CT(r);
     c.r2 = CT(r * r);
-    c.inv_r = CT(1.0 / r);
-    c.inv_r2 = CT(1.0 / (r * r));
+    c.hinv_r = CT(0.5 / r);
+    c.hinv_r2 = CT(0.5 / (r * r));
     c.rho0 = CT(p.rho0);
     c.c2 = CT(c2);
+    c.c2x2 = CT(2.0 * c2);
+    c.c2sq = CT(c2 * c2);
     c.c2rho0 = CT(c2 * p.rho0);
     c.ig1 = CT(1.0 / g - 1.0);
     c.Pg = CT(4.0 / (g * g) - 1.0 / g);
-    c.Qg = CT(1.0 / (g * g) - 1.0 / g);
+    c.Qg = CT(Qg);
     c.g3 = CT(1.0 / (g * g) - 3.0 / g + 2.0);
     c.Ab = CT(0.5 * (Ug * c2 - 1.0));
     c.Bb = CT(0.5 * (Ug * c2 - r * r));
@@ -75,17 +91,24 @@ inline Coef<CT> make_coef(const prc_params &p, int64_t pitch, int64_t plane)
     c.a2 = CT(3.0 * c2 - r * r);
     c.cb0 = CT(-2.0 * c2 / p.omega_xi);
     c.cs0 = CT(2.0 * c2 / p.omega_nu);
+    c.mhxi = CT(-hxi);
+    c.mhnu = CT(-hnu);
+    c.mhxi2 = CT(-2.0 * hxi);
+    c.mhnu2 = CT(-2.0 * hnu);
+    c.kq11 = CT(-Qg * hnu);
+    c.kl11 = CT(-(1.0 / g - 1.0) * hnu * c2);
     c.om_nu = CT(p.omega_nu);
     c.om_xi = CT(p.omega_xi);
     c.om_3 = CT(p.omega_3);
     c.om_4 = CT(p.omega_4);
-    c.hnu = CT(1.0 / p.omega_nu - 0.5);
-    c.hxi = CT(1.0 / p.omega_xi - 0.5);
     c.fxh = CT(p.fx / (2.0 * g));
     c.fyh = CT(p.fy / (2.0 * g));
-    c.qfx = CT((1.0 / (g * g) - 1.0 / g) * p.fx);
-    c.qfy = CT((1.0 / (g * g) - 1.0 / g) * p.fy);
-    c.sxi = CT(1.0 - 0.5 * p.omega_xi);
+    c.fxg = CT(p.fx / g);
+    c.fyg = CT(p.fy / g);
+    c.qfx = CT(Qg * p.fx);
+    c.qfy = CT(Qg * p.fy);
+    c.sxi2 = CT(2.0 - p.omega_xi);
+    c.snu2 = CT(2.0 - p.omega_nu);
     c.snu = CT(1.0 - 0.5 * p.omega_nu);
     c.lid = CT(p.rho0 * p.u_lid * c2 / (2.0 * r * r));
     c.gxa = CT(0.5 * (1.0 - c2 / (r * r)));

@@ -1,0 +1,187 @@
+// Per-node collision of the PRC-LBM (arXiv 2208.03562, Appendix A) on gfx950.
+//
+// The update is the appendix's f~ = P^-1 S^-1 F(-u) [m^c + B^-1 {Lambda (B
+// m^{c,eq} - B m^c) + (I - Lambda/2) B Phi^c}], m^c = F(u) S P f, evaluated in
+// an equivalent order chosen for few operations and small rounding errors:
+//
+//  * D2Q9 is the tensor product of two three-velocity lattices, and so are the
+//    maps of the appendix: P and S are products of one-dimensional maps and
+//    F(u) is the product of the binomial shifts along x and y.  The nine
+//    central moments are formed by a three-point transform along x for each
+//    row of the velocity set, then along y for each x-moment.
+//  * Since the whole map is linear in the moments, f~ = f + T^-1(dk), where
+//    T = F(u) S P and dk is the change of the central moments in the
+//    collision (zero for k00, F/gamma for k10 and k01).  Only the increments
+//    are transformed back, so the post-collision populations are the stored
+//    ones plus a small correction.
+//  * Populations are deviations from the rest state rho0 w.  The central
+//    moments of the deviations, plus the closed-form central moments of
+//    rho0 w about u minus rho0 (1,0,c2)x(1,0,c2), are the central moments of
+//    f minus that constant tensor; every equilibrium below is written minus
+//    the same constant, which cancels in each difference k_eq - k.
+//  * The correction terms of eq. 38-40 need rho times the strain rates of
+//    eq. 48; the coefficients of eq. 46 all carry a factor rho, so the solve
+//    is done for rho dxux, rho dyuy directly and rho never appears.
+#pragma once
+
+#include "prc_device.hpp"
+
+namespace prc {
+
+// FORCE: the body force may be nonzero.  ALL: every correction term is on
+// (the method); otherwise the correction bitmask is read at run time.
+template <typename CT, bool FORCE, bool ALL>
+__device__ __forceinline__ void collide(const Coef<CT> &c, CT d[9], CT gx, CT gy)
+{
+    CT q[3][3];  // [e_y + 1][e_x + 1]
+#pragma unroll
+    for (int a = 0; a < 9; ++a) q[QJ[a]][QI[a]] = d[a];
+
+    // raw x-moments of each row of the velocity set (eq. 62 along x)
+    CT X0[3], X1[3], X2[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        X1[j] = q[j][2] - q[j][0];
+        X2[j] = q[j][2] + q[j][0];
+        X0[j] = X2[j] + q[j][1];
+    }
+    // fields (eq. hydrodynamicfields); the y lattice speed is r (scaling S)
+    const CT drho = (X0[0] + X0[1]) + X0[2];
+    const CT rho = c.rho0 + drho;
+    const CT irho = recip(rho);
+    CT jx = (X1[0] + X1[1]) + X1[2], jy = c.r * (X0[2] - X0[0]);
+    if (FORCE) {
+        jx += c.fxh;
+        jy += c.fyh;
+    }
+    const CT ux = jx * irho, uy = jy * irho;
+    const CT ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
+
+    // central x-moments of each row: binomial shift by u_x
+    CT C1[3], C2[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        C1[j] = X1[j] - ux * X0[j];
+        C2[j] = X2[j] - ux * (X1[j] + C1[j]);
+    }
+    // central y-moments (lattice speed r) of each central x-moment
+    auto ytrans = [&](CT A, CT B, CT Cc, CT &K0, CT &K1, CT &K2) {
+        const CT Y1 = c.r * (Cc - A);
+        K0 = (A + B) + Cc;
+        K1 = Y1 - uy * K0;
+        K2 = c.r2 * (Cc + A) - uy * (Y1 + K1);
+    };
+    CT K00, K01, K02, K10, K11, K12, K20, K21, K22;
+    ytrans(X0[0], X0[1], X0[2], K00, K01, K02);
+    ytrans(C1[0], C1[1], C1[2], K10, K11, K12);
+    ytrans(C2[0], C2[1], C2[2], K20, K21, K22);
+    (void)K00;
+    (void)K01;
+    (void)K10;
+    // plus the central moments of rho0 w about u, minus rho0 (1,0,c2)x(1,0,c2)
+    const CT u2s = ux2 + uy2;
+    const CT k20 = K20 + c.rho0 * ux2;
+    const CT k02 = K02 + c.rho0 * uy2;
+    const CT k11 = K11 + c.rho0 * uxy;
+    const CT k21 = K21 - uy * (c.c2rho0 + c.rho0 * ux2);
+    const CT k12 = K12 - ux * (c.c2rho0 + c.rho0 * uy2);
+    const CT k22 = K22 + c.rho0 * (c.c2 * u2s + ux2 * uy2);
+
+    // combine (operator B)
+    const CT k2s = k20 + k02;  // minus 2 c2 rho0
+    const CT k2d = k20 - k02;
+
+    // preconditioned equilibria (eq. 14), minus the same constants
+    const CT irh = c.ig1 * rho;
+    const CT e2s = c.c2x2 * drho + irh * u2s;
+    const CT e2d = irh * (ux2 - uy2);
+    const CT e11 = irh * uxy;
+
+    // corrections (eq. 38-40) with the local strain rates (eq. 43-48)
+    CT cor2s = CT(0), cor2d = CT(0), cor11 = CT(0);
+    const int corr = ALL ? PRC_CORR_ALL : c.corr;
+    if (corr) {
+        const CT pux = c.Pg * ux2, puy = c.Pg * uy2, qux = c.Qg * ux2, quy = c.Qg * uy2;
+        const CT bx = (pux + quy) + c.a1, by = (puy + qux) + c.a2;
+        const CT sx = (pux - quy) + c.a1, sy = (puy - qux) + c.a2;
+        const CT Agx = c.Ab * ux * gx, Bgy = c.Bb * uy * gy;  // -e_b = Agx + Bgy
+        CT Dx = CT(0), Dy = CT(0);                            // rho dxux, rho dyuy
+        if (corr & (PRC_CORR_THETA | PRC_CORR_K11)) {
+            const CT R2s = (k2s - e2s) - (Agx + Bgy);
+            const CT R2d = (k2d - e2d) + (Bgy - Agx);
+            const CT cbx = c.cb0 + CT(0.5) * bx, cby = c.cb0 + CT(0.5) * by;
+            const CT csx = CT(0.5) * sx - c.cs0, csy = c.cs0 - CT(0.5) * sy;
+            const CT det = cbx * csy - csx * cby;
+            // one reciprocal serves both divisions of eq. 48
+            const CT ip = recip(det * cby);
+            Dx = (csy * R2s - cby * R2d) * (cby * ip);
+            Dy = (R2s - cbx * Dx) * (det * ip);
+        }
+        if (corr & PRC_CORR_THETA) {
+            // theta_bx = -bx rho h_xi, theta_by = -by rho h_xi, theta_sx =
+            // -sx rho h_nu, theta_sy = -sy rho h_nu; k2d takes theta_sx dxux
+            // - theta_sy dyuy
+            cor2s = c.mhxi * (bx * Dx + by * Dy);
+            cor2d = c.mhnu * (sx * Dx - sy * Dy);
+        }
+        if (corr & PRC_CORR_LAMBDA) {
+            cor2s += c.mhxi2 * (Agx + Bgy);
+            cor2d += c.mhnu2 * (Agx - Bgy);
+        }
+        if (corr & PRC_CORR_K11)
+            cor11 = c.kq11 * uxy * (Dx + Dy) + c.kl11 * (uy * gx + ux * gy);
+    }
+
+    // moment increments of the relaxation (Appendix A), B^-1 folded in
+    CT d2s = c.om_xi * ((e2s + cor2s) - k2s);
+    CT d2d = c.om_nu * ((e2d + cor2d) - k2d);
+    CT d11 = c.om_nu * ((e11 + cor11) - k11);
+    if (FORCE) {
+        // central source moments (eq. 13-central) with weights 1 - omega/2
+        d2s += c.sxi2 * (c.qfx * ux + c.qfy * uy);
+        d2d += c.snu2 * (c.qfx * ux - c.qfy * uy);
+        d11 += c.snu * (c.qfx * uy + c.qfy * ux);
+    }
+    const CT g3r = c.g3 * rho;
+    const CT d21 = c.om_3 * (g3r * ux2 * uy - k21);
+    const CT d12 = c.om_3 * (g3r * ux * uy2 - k12);
+    const CT d22 = c.om_4 * (c.c2sq * drho - k22);
+    const CT d20 = CT(0.5) * (d2s + d2d);
+    const CT d02 = CT(0.5) * (d2s - d2d);
+
+    // f~ = f + P^-1 S^-1 F(-u) dk: y-transform back for each x-moment ...
+    CT G[3][3];  // [x-moment][e_y + 1]
+    auto yinv = [&](CT K0, CT K1, CT K2, CT *g) {
+        const CT R1 = K1 + uy * K0;
+        const CT R2 = K2 + uy * (K1 + R1);
+        const CT a = c.hinv_r * R1, b = c.hinv_r2 * R2;  // halves
+        g[0] = b - a;
+        g[1] = K0 - CT(2) * b;
+        g[2] = b + a;
+    };
+    if (FORCE) {
+        // the first-order central moments change by F/gamma (k~10 = F/(2 gamma)
+        // for any omega_1, since k10 = -F/(2 gamma) by the definition of u)
+        yinv(CT(0), c.fyg, d02, G[0]);
+        yinv(c.fxg, d11, d12, G[1]);
+    } else {
+        yinv(CT(0), CT(0), d02, G[0]);
+        yinv(CT(0), d11, d12, G[1]);
+    }
+    yinv(d20, d21, d22, G[2]);
+    // ... then the x-transform back for each row, added to the populations
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const CT K0 = G[0][j], K1 = G[1][j], K2 = G[2][j];
+        const CT R1 = K1 + ux * K0;
+        const CT R2 = K2 + ux * (K1 + R1);
+        const CT h1 = CT(0.5) * R1, h2 = CT(0.5) * R2;
+        q[j][0] += h2 - h1;
+        q[j][1] += K0 - R2;
+        q[j][2] += h2 + h1;
+    }
+#pragma unroll
+    for (int a = 0; a < 9; ++a) d[a] = q[QJ[a]][QI[a]];
+}
+
+}  // namespace prc

@@ -22,6 +22,7 @@
 #include "prc.h"
 #include "prc_coef.hpp"
 #include "prc_device.hpp"
+#include "prc_sweep.hpp"
 
 namespace prc {
 
@@ -50,8 +51,6 @@ static prc_status fail(prc_status s, const char *fmt, ...)
 
 // ---------------------------------------------------------------- layout --
 constexpr int kPitchAlignBytes = 256;
-constexpr int kSweepTX = 64;   // one wavefront per tile row
-constexpr int kSweepTY = 4;
 constexpr int kRedBlock = 256;
 constexpr int kRedMaxBlocks = 1024;
 
@@ -64,11 +63,47 @@ static size_t elem_bytes(int storage)
     }
 }
 
-static void layout(const prc_params &p, int64_t &pitch, int64_t &plane)
+// State layouts (element (a, j, i) at a * plane + j * row + i):
+//   0  plane-major: nine whole planes one after the other
+//   1  plane-major with each plane padded by kPlanePadBytes, so that the nine
+//      loads of a node do not all fall on addresses a power of two apart
+//   2  row-interleaved: row j of all nine planes stored together
+//      ([j][a][i]), so a tile's loads and stores stay within a few DRAM pages
+constexpr int kLayoutDefault = 2;
+constexpr int64_t kPlanePadBytes = 4096 + 256;
+
+static int layout_mode()
 {
-    const int64_t per = kPitchAlignBytes / (int64_t)elem_bytes(p.storage);
-    pitch = ((int64_t)p.nx + per - 1) / per * per;
-    plane = pitch * p.ny;
+    static const int v = [] {
+        const char *e = std::getenv("PRC_LAYOUT");
+        const int m = e ? std::atoi(e) : kLayoutDefault;
+        return (m >= 0 && m <= 2) ? m : kLayoutDefault;
+    }();
+    return v;
+}
+
+// row and plane strides and total size, in elements
+static void layout(const prc_params &p, int64_t &row, int64_t &plane, int64_t &total)
+{
+    const int64_t E = (int64_t)elem_bytes(p.storage);
+    const int64_t per = kPitchAlignBytes / E;
+    const int64_t pitch = ((int64_t)p.nx + per - 1) / per * per;
+    switch (layout_mode()) {
+    case 1:
+        row = pitch;
+        plane = pitch * p.ny + kPlanePadBytes / E;
+        total = 9 * plane;
+        break;
+    case 2:
+        row = 9 * pitch;
+        plane = pitch;
+        total = row * p.ny;
+        break;
+    default:
+        row = pitch;
+        plane = pitch * p.ny;
+        total = 9 * plane;
+    }
 }
 
 static prc_status validate(const prc_params *p)
@@ -94,6 +129,11 @@ static prc_status validate(const prc_params *p)
         return fail(PRC_EINVAL, "corrections bitmask out of range");
     if (p->frame != PRC_FRAME_CENTRAL)
         return fail(PRC_EINVAL, "frame %d is not available in this library", p->frame);
+    int64_t row, plane, total;
+    layout(*p, row, plane, total);
+    // byte offsets into one state buffer are 32-bit (buffer addressing)
+    if (total * (int64_t)elem_bytes(p->storage) > (int64_t)0xFFFFFFFF)
+        return fail(PRC_EINVAL, "state of %d x %d exceeds 4 GiB", p->nx, p->ny);
     return PRC_OK;
 }
 
@@ -104,91 +144,26 @@ static prc_status check_buf(const void *b, const char *name)
     return PRC_OK;
 }
 
+template <typename ST>
+static Coef<typename Mem<ST>::CT> coef_of(const prc_params &p)
+{
+    int64_t row, plane, total;
+    layout(p, row, plane, total);
+    return make_coef<typename Mem<ST>::CT>(p, row, plane, total, (int64_t)sizeof(ST));
+}
+
 // ------------------------------------------------------------- kernels --
 
-// XCD-aware tile order: the hardware hands workgroup i to XCD i mod 8, so
-// workgroup i takes logical tile (i mod 8) * per + i / 8.  Each XCD then owns
-// one contiguous band of tile rows, and the density halo a tile shares with
-// the tiles above and below it is read through the same L2.
-__device__ __forceinline__ bool map_tile(int tiles, int per, int &tile)
+template <typename ST, int BC>
+__global__ void k_macros(const ST *__restrict__ f, const Coef<typename Mem<ST>::CT> c, double *rho,
+                         double *ux, double *uy)
 {
-    const int i = blockIdx.x;
-    tile = (i % kXcds) * per + i / kXcds;
-    return tile < tiles;
-}
-
-template <typename ST, typename CT, int BC, int TX, int TY>
-__global__ void __launch_bounds__(TX *TY)
-    k_sweep(const ST *__restrict__ src, ST *__restrict__ dst, const Coef<CT> c)
-{
-    __shared__ CT srho[TY + 2][TX + 2];
-    int tile;
-    if (!map_tile(c.tiles_x * c.tiles_y, c.tiles_per_xcd, tile)) return;
-    const int x0 = (tile % c.tiles_x) * TX, y0 = (tile / c.tiles_x) * TY;
-    const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
-    const int x = x0 + tx, y = y0 + ty;
-    // every source of every node of the tile and of its one-node ring lies
-    // inside the domain: no boundary logic needed
-    const bool inner = x0 >= 2 && y0 >= 2 && x0 + TX + 2 <= c.nx && y0 + TY + 2 <= c.ny;
-    const bool active = x < c.nx && y < c.ny;
-
-    CT d[9];
-    if (inner) {
-        pull<ST, CT, BC, false>(c, src, x, y, d);
-    } else {
-        int fx = x, fy = y;
-        fix_coord<BC>(fx, fy, c.nx, c.ny);  // inactive slots stand in for their image
-        pull<ST, CT, BC, true>(c, src, fx, fy, d);
-    }
-    srho[ty + 1][tx + 1] = sum9(d);
-
-    // densities of the one-node ring around the tile
-    constexpr int RING = 2 * (TX + 2) + 2 * TY;
-    for (int k = tid; k < RING; k += TX * TY) {
-        int hx, hy;
-        if (k < TX + 2) { hx = k - 1; hy = -1; }
-        else if (k < 2 * (TX + 2)) { hx = k - (TX + 2) - 1; hy = TY; }
-        else if (k < 2 * (TX + 2) + TY) { hx = -1; hy = k - 2 * (TX + 2); }
-        else { hx = TX; hy = k - 2 * (TX + 2) - TY; }
-        CT e[9];
-        if (inner) {
-            pull<ST, CT, BC, false>(c, src, x0 + hx, y0 + hy, e);
-        } else {
-            int gx = x0 + hx, gy = y0 + hy;
-            fix_coord<BC>(gx, gy, c.nx, c.ny);
-            pull<ST, CT, BC, true>(c, src, gx, gy, e);
-        }
-        srho[hy + 1][hx + 1] = sum9(e);
-    }
-    __syncthreads();
-    if (!active) return;
-
-    // density gradient: rest-weighted central differences over the eight
-    // neighbours (exact for linear rho; [4,1,1]/12 at r = 1)
-    const int lx = tx + 1, ly = ty + 1;
-    const CT rE = srho[ly][lx + 1], rW = srho[ly][lx - 1];
-    const CT rN = srho[ly + 1][lx], rS = srho[ly - 1][lx];
-    const CT rNE = srho[ly + 1][lx + 1], rNW = srho[ly + 1][lx - 1];
-    const CT rSE = srho[ly - 1][lx + 1], rSW = srho[ly - 1][lx - 1];
-    const CT gx = c.gxa * (rE - rW) + c.gxb * ((rNE - rNW) + (rSE - rSW));
-    const CT gy = c.gya * (rN - rS) + c.gyb * ((rNE + rNW) - (rSE + rSW));
-
-    collide<CT>(c, d, gx, gy);
-
-    const int64_t o = (int64_t)y * c.pitch + x;
-#pragma unroll
-    for (int a = 0; a < 9; ++a) dst[a * c.plane + o] = Conv<ST, CT>::st(d[a]);
-}
-
-template <typename ST, typename CT, int BC>
-__global__ void k_macros(const ST *__restrict__ f, const Coef<CT> c, double *rho, double *ux,
-                         double *uy)
-{
+    using CT = typename Mem<ST>::CT;
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= (int64_t)c.nx * c.ny) return;
     const int x = (int)(n % c.nx), y = (int)(n / c.nx);
     CT d[9];
-    pull<ST, CT, BC, true>(c, f, x, y, d);
+    pull_checked<ST, BC>(c, make_rsrc(f, c.state_bytes), x, y, d);
     CT drho, u, v;
     fields(c, d, drho, u, v);
     if (rho) rho[n] = (double)c.rho0 + (double)drho;
@@ -216,19 +191,21 @@ __device__ __forceinline__ void block_reduce4(double v[4], double *sh /* [4][kRe
     for (int k = 0; k < 4; ++k) v[k] = sh[k * kRedBlock];
 }
 
-template <typename ST, typename CT, int BC>
+template <typename ST, int BC>
 __global__ void __launch_bounds__(kRedBlock)
-    k_residual(const ST *__restrict__ f, const Coef<CT> c, double *__restrict__ u_prev,
-               double *__restrict__ partial)
+    k_residual(const ST *__restrict__ f, const Coef<typename Mem<ST>::CT> c,
+               double *__restrict__ u_prev, double *__restrict__ partial)
 {
+    using CT = typename Mem<ST>::CT;
     __shared__ double sh[4 * kRedBlock];
     const int64_t N = (int64_t)c.nx * c.ny;
+    const rsrc_t rs = make_rsrc(f, c.state_bytes);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int64_t n = (int64_t)blockIdx.x * kRedBlock + threadIdx.x; n < N;
          n += (int64_t)gridDim.x * kRedBlock) {
         const int x = (int)(n % c.nx), y = (int)(n / c.nx);
         CT d[9];
-        pull<ST, CT, BC, true>(c, f, x, y, d);
+        pull_checked<ST, BC>(c, rs, x, y, d);
         CT drho, u, v;
         fields(c, d, drho, u, v);
         const double du = (double)u - u_prev[n], dv = (double)v - u_prev[N + n];
@@ -263,38 +240,93 @@ __global__ void __launch_bounds__(kRedBlock)
 }
 
 // ------------------------------------------------------------ dispatch --
-template <typename ST> struct ComputeOf { using type = float; };
-template <> struct ComputeOf<double> { using type = double; };
+
+// Sweep tile shapes (threads along x, along y).  A taller tile needs fewer
+// ring densities per node; a wider one gives longer contiguous row segments.
+struct TileShape {
+    int tx, ty;
+};
+constexpr TileShape kTiles[] = {{64, 4}, {64, 8}, {128, 4}};
+constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
+
+// Tile shape per problem: what prc_tune measured for this grid, else a
+// default (wide tiles for wide grids); PRC_TILE=<index> forces one shape.
+static std::mutex g_tune_mu;
+static std::unordered_map<std::string, int> g_tuned;
+
+static std::string tune_key(const prc_params &p)
+{
+    char k[96];
+    std::snprintf(k, sizeof k, "%d/%d/%d/%d/%d", p.storage, p.bc, p.nx, p.ny, layout_mode());
+    return k;
+}
+
+static int tile_choice(const prc_params &p)
+{
+    static const int forced = [] {
+        const char *e = std::getenv("PRC_TILE");
+        const int i = e ? std::atoi(e) : -1;
+        return (i >= 0 && i < kNumTiles) ? i : -1;
+    }();
+    if (forced >= 0) return forced;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        auto it = g_tuned.find(tune_key(p));
+        if (it != g_tuned.end()) return it->second;
+    }
+    return p.nx >= 256 ? 2 : 0;
+}
+
+template <typename ST, int BC, int TX, int TY, bool FORCE, bool ALL>
+static prc_status launch_sweep_shape(const prc_params &p, const void *src, void *dst, hipStream_t s)
+{
+    auto c = coef_of<ST>(p);
+    c.tiles_x = (p.nx + TX - 1) / TX;
+    c.tiles_y = (p.ny + TY - 1) / TY;
+    const int tiles = c.tiles_x * c.tiles_y;
+    c.tiles_per_xcd = (tiles + kXcds - 1) / kXcds;
+    hipLaunchKernelGGL((k_sweep<ST, BC, TX, TY, FORCE, ALL>), dim3(c.tiles_per_xcd * kXcds),
+                       dim3(TX * TY), 0, s, (const ST *)src, (ST *)dst, c);
+    HIP_TRY(hipGetLastError());
+    return PRC_OK;
+}
+
+// The method itself (every correction, no body force) runs a specialised
+// kernel; any other correction mask or a body force runs the general one.
+template <typename ST, int BC, int TX, int TY>
+static prc_status launch_sweep_variant(const prc_params &p, const void *src, void *dst,
+                                       hipStream_t s)
+{
+    if (p.corrections == PRC_CORR_ALL && p.fx == 0.0 && p.fy == 0.0)
+        return launch_sweep_shape<ST, BC, TX, TY, false, true>(p, src, dst, s);
+    return launch_sweep_shape<ST, BC, TX, TY, true, false>(p, src, dst, s);
+}
+
+template <typename ST, int BC>
+static prc_status launch_sweep_tile(const prc_params &p, int tile, const void *src, void *dst,
+                                    hipStream_t s)
+{
+    switch (tile) {
+    case 1: return launch_sweep_variant<ST, BC, 64, 8>(p, src, dst, s);
+    case 2: return launch_sweep_variant<ST, BC, 128, 4>(p, src, dst, s);
+    default: return launch_sweep_variant<ST, BC, 64, 4>(p, src, dst, s);
+    }
+}
 
 template <typename ST, int BC>
 static prc_status launch_sweep(const prc_params &p, const void *src, void *dst, hipStream_t s)
 {
-    using CT = typename ComputeOf<ST>::type;
-    int64_t pitch, plane;
-    layout(p, pitch, plane);
-    Coef<CT> c = make_coef<CT>(p, pitch, plane);
-    c.tiles_x = (p.nx + kSweepTX - 1) / kSweepTX;
-    c.tiles_y = (p.ny + kSweepTY - 1) / kSweepTY;
-    const int tiles = c.tiles_x * c.tiles_y;
-    c.tiles_per_xcd = (tiles + kXcds - 1) / kXcds;
-    const int blocks = c.tiles_per_xcd * kXcds;
-    hipLaunchKernelGGL((k_sweep<ST, CT, BC, kSweepTX, kSweepTY>), dim3(blocks),
-                       dim3(kSweepTX * kSweepTY), 0, s, (const ST *)src, (ST *)dst, c);
-    HIP_TRY(hipGetLastError());
-    return PRC_OK;
+    return launch_sweep_tile<ST, BC>(p, tile_choice(p), src, dst, s);
 }
 
 template <typename ST, int BC>
 static prc_status launch_macros(const prc_params &p, const void *f, double *rho, double *ux,
                                 double *uy, hipStream_t s)
 {
-    using CT = typename ComputeOf<ST>::type;
-    int64_t pitch, plane;
-    layout(p, pitch, plane);
-    const Coef<CT> c = make_coef<CT>(p, pitch, plane);
+    const auto c = coef_of<ST>(p);
     const int64_t N = (int64_t)p.nx * p.ny;
-    hipLaunchKernelGGL((k_macros<ST, CT, BC>), dim3((unsigned)((N + 255) / 256)), dim3(256), 0,
-                       s, (const ST *)f, c, rho, ux, uy);
+    hipLaunchKernelGGL((k_macros<ST, BC>), dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s,
+                       (const ST *)f, c, rho, ux, uy);
     HIP_TRY(hipGetLastError());
     return PRC_OK;
 }
@@ -310,12 +342,9 @@ template <typename ST, int BC>
 static prc_status launch_residual(const prc_params &p, const void *f, double *u_prev,
                                   double *scratch, hipStream_t s)
 {
-    using CT = typename ComputeOf<ST>::type;
-    int64_t pitch, plane;
-    layout(p, pitch, plane);
-    const Coef<CT> c = make_coef<CT>(p, pitch, plane);
+    const auto c = coef_of<ST>(p);
     const int nb = red_blocks(p);
-    hipLaunchKernelGGL((k_residual<ST, CT, BC>), dim3(nb), dim3(kRedBlock), 0, s, (const ST *)f, c,
+    hipLaunchKernelGGL((k_residual<ST, BC>), dim3(nb), dim3(kRedBlock), 0, s, (const ST *)f, c,
                        u_prev, scratch);
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(kRedBlock), 0, s, (const double *)scratch, nb,
@@ -466,21 +495,22 @@ prc_status prc_params_from_re(prc_params *p, double re)
 
 prc_status prc_validate(const prc_params *p) { return validate(p); }
 
-prc_status prc_layout(const prc_params *p, int64_t *pitch, int64_t *plane)
+prc_status prc_layout(const prc_params *p, int64_t *row_stride, int64_t *plane_stride)
 {
     prc_status st = validate(p);
     if (st != PRC_OK) return st;
-    if (!pitch || !plane) return fail(PRC_EINVAL, "NULL output");
-    layout(*p, *pitch, *plane);
+    if (!row_stride || !plane_stride) return fail(PRC_EINVAL, "NULL output");
+    int64_t total;
+    layout(*p, *row_stride, *plane_stride, total);
     return PRC_OK;
 }
 
 size_t prc_state_bytes(const prc_params *p)
 {
     if (validate(p) != PRC_OK) return 0;
-    int64_t pitch, plane;
-    layout(*p, pitch, plane);
-    return (size_t)(9 * plane) * elem_bytes(p->storage);
+    int64_t row, plane, total;
+    layout(*p, row, plane, total);
+    return (size_t)total * elem_bytes(p->storage);
 }
 
 size_t prc_scratch_bytes(const prc_params *p)
@@ -595,6 +625,65 @@ prc_status prc_solve(const prc_params *p, void *f_a, void *f_b, double *u_prev, 
     *steps_out = n;
     if (hist_len) *hist_len = nh;
     return result;
+}
+
+prc_status prc_tune(const prc_params *p, int32_t *tile_out, hipStream_t stream)
+{
+    prc_status st = validate(p);
+    if (st != PRC_OK) return st;
+    constexpr int kWarm = 4, kTimed = 20;
+    const size_t bytes = prc_state_bytes(p);
+    void *a = nullptr, *b = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int best = -1;
+    float best_ms = 0.0f;
+    hipError_t he = hipMalloc(&a, bytes);
+    if (he == hipSuccess) he = hipMalloc(&b, bytes);
+    if (he == hipSuccess) he = hipMemsetAsync(a, 0, bytes, stream);
+    if (he == hipSuccess) he = hipMemsetAsync(b, 0, bytes, stream);
+    if (he == hipSuccess) he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    for (int t = 0; t < kNumTiles && he == hipSuccess && st == PRC_OK; ++t) {
+        for (int k = 0; k < kWarm + kTimed && st == PRC_OK; ++k) {
+            if (k == kWarm) he = hipEventRecord(e0, stream);
+            st = PRC_DISPATCH(*p, launch_sweep_tile, *p, t, (k & 1) ? b : a, (k & 1) ? a : b,
+                              stream);
+        }
+        if (st != PRC_OK || he != hipSuccess) break;
+        he = hipEventRecord(e1, stream);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (he == hipSuccess && (best < 0 || ms < best_ms)) {
+            best = t;
+            best_ms = ms;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (a) (void)hipFree(a);
+    if (b) (void)hipFree(b);
+    if (st != PRC_OK) return st;
+    if (he != hipSuccess) return fail(PRC_EHIP, "prc_tune: %s", hipGetErrorString(he));
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tuned[tune_key(*p)] = best;
+    }
+    if (tile_out) *tile_out = best;
+    return PRC_OK;
+}
+
+prc_status prc_set_tile(const prc_params *p, int32_t tile)
+{
+    prc_status st = validate(p);
+    if (st != PRC_OK) return st;
+    if (tile < -1 || tile >= kNumTiles) return fail(PRC_EINVAL, "tile %d out of range", tile);
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    if (tile < 0)
+        g_tuned.erase(tune_key(*p));
+    else
+        g_tuned[tune_key(*p)] = tile;
+    return PRC_OK;
 }
 
 prc_status prc_release_graphs(void)

@@ -1,0 +1,121 @@
+// Sweep kernels: one fused PRC-LBM time step over a grid of tiles.
+//
+// A tile is TX x TY nodes, one node per thread.  Each thread streams its node
+// (pull with boundaries); the first RING threads also stream one node of the
+// one-node ring around the tile, because the density gradient at a node needs
+// the streamed densities of its eight neighbours at the same time level.  The
+// densities go to an LDS tile, one barrier, then each thread computes the
+// gradient, collides and stores its node.
+//
+// k_sweep      one tile per workgroup (the grid covers all tiles once)
+#pragma once
+
+#include "prc_collide.hpp"
+#include "prc_device.hpp"
+
+namespace prc {
+
+template <int TX, int TY>
+struct TileGeom {
+    static constexpr int RING = 2 * (TX + 2) + 2 * TY;
+    static_assert(TX * TY >= RING, "one ring node per thread at most");
+    int tx, ty;   // this thread's node in the tile
+    int hx, hy;   // this thread's ring node (tile-relative), if ring
+    bool ring;
+
+    __device__ __forceinline__ explicit TileGeom(int tid)
+    {
+        tx = tid % TX;
+        ty = tid / TX;
+        ring = tid < RING;
+        if (tid < TX + 2) { hx = tid - 1; hy = -1; }
+        else if (tid < 2 * (TX + 2)) { hx = tid - (TX + 2) - 1; hy = TY; }
+        else if (tid < 2 * (TX + 2) + TY) { hx = -1; hy = tid - 2 * (TX + 2); }
+        else { hx = TX; hy = tid - 2 * (TX + 2) - TY; }
+    }
+};
+
+// Issue the loads of this thread's node and ring node of the tile at (x0, y0).
+template <typename ST, int BC, int TX, int TY>
+__device__ __forceinline__ void tile_load(const Coef<typename Mem<ST>::CT> &c, rsrc_t rs,
+                                          const TileGeom<TX, TY> &g, int x0, int y0,
+                                          typename Mem<ST>::CT d[9],
+                                          typename Mem<ST>::CT e[9])
+{
+    constexpr uint32_t E = sizeof(ST);
+    // every source of every node of the tile and of its ring lies inside the
+    // grid: no boundary logic needed
+    const bool inner = x0 >= 2 && y0 >= 2 && x0 + TX + 2 <= c.nx && y0 + TY + 2 <= c.ny;
+    int x = x0 + g.tx, y = y0 + g.ty, rx = x0 + g.hx, ry = y0 + g.hy;
+    if (inner) {
+        pull_inner<ST>(c, rs, (uint32_t)y * c.row_bytes + (uint32_t)(x - 1) * E, d);
+        if (g.ring) pull_inner<ST>(c, rs, (uint32_t)ry * c.row_bytes + (uint32_t)(rx - 1) * E, e);
+    } else {
+        fix_coord<BC>(x, y, c.nx, c.ny);  // slots beyond the grid stand in for their image
+        pull_checked<ST, BC>(c, rs, x, y, d);
+        if (g.ring) {
+            fix_coord<BC>(rx, ry, c.nx, c.ny);
+            pull_checked<ST, BC>(c, rs, rx, ry, e);
+        }
+    }
+}
+
+template <typename CT, int TX, int TY>
+__device__ __forceinline__ void tile_densities(CT (*srho)[TX + 2], const TileGeom<TX, TY> &g,
+                                               const CT d[9], const CT e[9])
+{
+    srho[g.ty + 1][g.tx + 1] = sum9(d);
+    if (g.ring) srho[g.hy + 1][g.hx + 1] = sum9(e);
+}
+
+// Density gradient, collision and store of this thread's node (after the
+// barrier that publishes the LDS densities).
+template <typename ST, int TX, int TY, bool FORCE, bool ALL>
+__device__ __forceinline__ void tile_finish(const Coef<typename Mem<ST>::CT> &c, rsrc_t rd,
+                                            const typename Mem<ST>::CT (*srho)[TX + 2],
+                                            const TileGeom<TX, TY> &g, int x0, int y0,
+                                            typename Mem<ST>::CT d[9])
+{
+    using CT = typename Mem<ST>::CT;
+    constexpr uint32_t E = sizeof(ST);
+    const int x = x0 + g.tx, y = y0 + g.ty;
+    if (x >= c.nx || y >= c.ny) return;
+    // rest-weighted central differences over the eight neighbours (exact for
+    // linear rho; the [4,1,1]/12 stencil at r = 1)
+    const int lx = g.tx + 1, ly = g.ty + 1;
+    const CT rE = srho[ly][lx + 1], rW = srho[ly][lx - 1];
+    const CT rN = srho[ly + 1][lx], rS = srho[ly - 1][lx];
+    const CT rNE = srho[ly + 1][lx + 1], rNW = srho[ly + 1][lx - 1];
+    const CT rSE = srho[ly - 1][lx + 1], rSW = srho[ly - 1][lx - 1];
+    const CT gx = c.gxa * (rE - rW) + c.gxb * ((rNE - rNW) + (rSE - rSW));
+    const CT gy = c.gya * (rN - rS) + c.gyb * ((rNE + rNW) - (rSE + rSW));
+
+    collide<CT, FORCE, ALL>(c, d, gx, gy);
+
+    const uint32_t o = (uint32_t)y * c.row_bytes + (uint32_t)x * E;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) Mem<ST>::st(rd, o, a * c.plane_bytes, d[a]);
+}
+
+// XCD-aware tile order: the hardware hands workgroup i to XCD i mod 8.  Each
+// XCD owns one contiguous band of tiles (tiles_per_xcd of them, row-major),
+// so the density halo a tile shares with the tiles above and below is read
+// through the same L2.
+template <typename ST, int BC, int TX, int TY, bool FORCE, bool ALL>
+__global__ void __launch_bounds__(TX *TY)
+    k_sweep(const ST *__restrict__ src, ST *__restrict__ dst, const Coef<typename Mem<ST>::CT> c)
+{
+    using CT = typename Mem<ST>::CT;
+    __shared__ CT srho[TY + 2][TX + 2];
+    const int tile = (blockIdx.x % kXcds) * c.tiles_per_xcd + blockIdx.x / kXcds;
+    if (tile >= c.tiles_x * c.tiles_y) return;
+    const int x0 = (tile % c.tiles_x) * TX, y0 = (tile / c.tiles_x) * TY;
+    const TileGeom<TX, TY> g(threadIdx.x);
+    CT d[9], e[9];
+    tile_load<ST, BC>(c, make_rsrc(src, c.state_bytes), g, x0, y0, d, e);
+    tile_densities<CT>(srho, g, d, e);
+    __syncthreads();
+    tile_finish<ST, TX, TY, FORCE, ALL>(c, make_rsrc(dst, c.state_bytes), srho, g, x0, y0, d);
+}
+
+}  // namespace prc

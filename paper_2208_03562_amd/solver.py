@@ -38,12 +38,13 @@ class Solver:
         capi.prc_validate(p)
         self.p = p.copy()
         self.device = torch.device(device)
-        self.pitch, self.plane = capi.prc_layout(self.p)
+        self.row_stride, self.plane_stride = capi.prc_layout(self.p)
         dt = TORCH_DTYPE[self.p.storage]
-        shape = (9, self.p.ny, self.pitch)
-        assert 9 * self.plane * torch.tensor([], dtype=dt).element_size() == capi.prc_state_bytes(self.p)
-        self.fa = torch.empty(shape, dtype=dt, device=self.device)
-        self.fb = torch.empty(shape, dtype=dt, device=self.device)
+        nbytes = capi.prc_state_bytes(self.p)
+        esize = torch.tensor([], dtype=dt).element_size()
+        assert nbytes % esize == 0
+        self.fa = torch.empty(nbytes // esize, dtype=dt, device=self.device)
+        self.fb = torch.empty(nbytes // esize, dtype=dt, device=self.device)
         self.u_prev = torch.zeros((2, self.p.ny, self.p.nx), dtype=torch.float64, device=self.device)
         self.scratch = torch.empty(capi.prc_scratch_bytes(self.p), dtype=torch.uint8,
                                    device=self.device)
@@ -67,16 +68,20 @@ class Solver:
         capi.prc_init(self.p, self.fb.data_ptr(), self.s)
         self.steps = 0
 
+    def view(self, buf: torch.Tensor) -> torch.Tensor:
+        """[9][ny][nx] view of a state buffer (the library's strides)."""
+        return torch.as_strided(buf, (9, self.p.ny, self.p.nx), (self.plane_stride, self.row_stride, 1))
+
     def set_state(self, dev) -> None:
         """Load deviations f - rho0 w (array [9][ny][nx]) as the current state."""
         t = torch.as_tensor(dev).to(device=self.device, dtype=self.fa.dtype)
         assert t.shape == (9, self.p.ny, self.p.nx)
         with torch.cuda.stream(self.stream):
-            self.current()[:, :, : self.p.nx].copy_(t)
+            self.view(self.current()).copy_(t)
 
     def get_state(self) -> torch.Tensor:
         with torch.cuda.stream(self.stream):
-            out = self.current()[:, :, : self.p.nx].to(torch.float64)
+            out = self.view(self.current()).to(torch.float64)
         self.stream.synchronize()
         return out
 

@@ -89,10 +89,12 @@ def test_lid_speed_limit_uses_rectangular_sound_speed():
 def test_layout_and_sizes(storage, elem):
     p = base()
     p.nx, p.ny, p.storage = 1000, 37, storage
-    pitch, plane = capi.prc_layout(p)
-    assert pitch >= 1000 and (pitch * elem) % 256 == 0 and pitch * elem - 1000 * elem < 256
-    assert plane == pitch * 37
-    assert capi.prc_state_bytes(p) == 9 * plane * elem
+    row, plane = capi.prc_layout(p)
+    # every element (a, j, i) lies inside the buffer and no two coincide
+    offs = sorted(a * plane + j * row + i for a in range(9) for j in range(37) for i in (0, 999))
+    assert offs[0] == 0 and len(set(offs)) == len(offs)
+    assert (offs[-1] + 1) * elem <= capi.prc_state_bytes(p)
+    assert (row * elem) % 256 == 0 and (plane * elem) % 256 == 0
     assert capi.prc_scratch_bytes(p) > 0
 
 
@@ -104,3 +106,11 @@ def test_from_re_rejects_bad_input():
     p.u_lid = 0.05
     with pytest.raises(capi.PrcError):
         capi.prc_params_from_re(p, -1.0)
+
+
+def test_set_tile_validates_without_gpu():
+    p = base()
+    capi.prc_set_tile(p, 1)
+    capi.prc_set_tile(p, -1)
+    with pytest.raises(capi.PrcError):
+        capi.prc_set_tile(p, 7)

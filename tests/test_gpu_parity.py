@@ -241,3 +241,35 @@ def test_mass_conserved_f32(torch_cuda):
     sol.step(4000)
     m1 = sol.residual()[2]
     assert abs(m1 / m0 - 1.0) < 1e-7
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_tile_shapes_give_identical_results(O, torch_cuda, storage):
+    """The tile shape only changes how nodes are grouped into workgroups:
+    every shape must produce the same bits."""
+    from paper_2208_03562_amd import capi
+    s = spec(300, 70, 2.0, 0.3, omega_nu=1.3, u_lid=0.05, storage=storage)
+    noise = workloads.deviation_noise(300, 70, seed=11, amplitude=1e-3)
+    outs = []
+    for tile in range(3):
+        sol = make_solver(s)
+        capi.prc_set_tile(sol.p, tile)
+        sol.set_state(noise)
+        sol.step(7)
+        outs.append(sol.get_state())
+    capi.prc_set_tile(sol.p, -1)
+    for o in outs[1:]:
+        assert bool((o == outs[0]).all())
+
+
+def test_tune_returns_a_shape_and_results_are_unchanged(torch_cuda):
+    from paper_2208_03562_amd import capi
+    s = spec(520, 130, 2.0, 0.2, omega_nu=1.1, u_lid=0.05, storage="f32")
+    a = make_solver(s)
+    a.step(6)
+    t = capi.prc_tune(a.p)
+    assert t in (0, 1, 2)
+    b = make_solver(s)
+    b.step(6)
+    capi.prc_set_tile(a.p, -1)
+    assert bool((a.get_state() == b.get_state()).all())

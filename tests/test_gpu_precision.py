@@ -1,0 +1,77 @@
+"""Reduced-precision storage (FP16 and BF16 deviations, FP32 arithmetic)
+against the FP64 oracle, with FP32 storage as the yardstick.
+
+Bounds, from the storage formats: a value rounded to FP16 carries a relative
+error up to 2^-11 (4.9e-4), to BF16 up to 2^-8 (3.9e-3).  One step from a
+random state therefore differs from the oracle by about that fraction of the
+largest deviation; over a flow the errors stay bounded because the collision
+damps them, and the velocity error is stated relative to the lid speed.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from tests.common import lib_params, max_rel_velocity_error, oracle_deviation, oracle_params, spec
+
+pytestmark = pytest.mark.gpu
+
+ROUND = {"f32": lambda a: a.astype(np.float32).astype(np.float64),
+         "f16": lambda a: torch.from_numpy(a).to(torch.float16).double().numpy(),
+         "bf16": lambda a: torch.from_numpy(a).to(torch.bfloat16).double().numpy()}
+ONE_STEP_BOUND = {"f32": 1e-5, "f16": 2e-3, "bf16": 1.6e-2}
+
+
+def make_solver(s):
+    from paper_2208_03562_amd import solver
+    return solver.Solver(lib_params(s))
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16", "f32"])
+@pytest.mark.parametrize("bc,r,gamma", [("cavity", 0.5, 0.05), ("periodic", 2.0, 0.3),
+                                        ("channel", 1.0, 1.0)])
+def test_one_step_from_random_state(O, storage, bc, r, gamma):
+    s = spec(200, 40, r, gamma, omega_nu=1.2, bc=bc, storage=storage,
+             u_lid=0.0 if bc == "periodic" else 0.01)
+    noise = ROUND[storage](workloads.deviation_noise(200, 40, seed=17, amplitude=2e-3))
+    sol = make_solver(s)
+    sol.set_state(noise)
+    po = oracle_params(O, s)
+    ft = np.ascontiguousarray(O.rest_state(po) + noise)
+    sol.step(1)
+    O.step(po, ft, 1)
+    dev = oracle_deviation(O, po, ft)
+    err = np.abs(sol.get_state().cpu().numpy() - dev).max() / np.abs(dev).max()
+    assert err < ONE_STEP_BOUND[storage], err
+
+
+TRAJ_BOUND = {"f32": 1e-5, "f16": 5e-3, "bf16": 8e-2}
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_shallow_cavity_trajectory(O, storage):
+    """The 4096 x 2048 shallow cavity scaled down 16x per side (256 x 128,
+    r = 0.5, Re = 125, gamma = 0.05) at Ma = 0.06: 3000 steps from rest."""
+    U = workloads.MA006_LID_R05
+    s = spec(256, 128, 0.5, 0.05, omega_nu=None, re=2000.0 / 16, u_lid=U, storage=storage)
+    sol = make_solver(s)
+    sol.step(3000)
+    po = oracle_params(O, s)
+    ft = O.rest_state(po)
+    O.step(po, ft, 3000)
+    _, ux, uy = (a.cpu().numpy() for a in sol.macros())
+    _, oux, ouy = O.velocity(po, ft)
+    err = max_rel_velocity_error(ux, uy, oux, ouy, U)
+    print(f"{storage}: max |u - u_oracle| / U = {err:.3e}")
+    assert err < TRAJ_BOUND[storage], err
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_named_4096x2048_16bit_config_diverges(storage):
+    """Ma = 0.17 with gamma = 0.05 is unstable for the scheme in any
+    precision; the solve reports the divergence at the first check."""
+    w = workloads.CAVITY_4096x2048_F16
+    s = spec(w.nx, w.ny, w.r, w.gamma, omega_nu=None, re=w.re, u_lid=w.u_lid, storage=storage)
+    sol = make_solver(s)
+    st, n, _ = sol.solve(1e-8, 500, 1000)
+    assert st == -3 and n == 500
