@@ -35,3 +35,12 @@ def build(verbose: bool = False) -> str:
 
 if __name__ == "__main__":
     print(build(verbose=True))
+
+
+def source_hash() -> str:
+    """Hash of the library's sources (identifies the kernel a profile was taken on)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(SOURCES + HEADERS):
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
