@@ -27,6 +27,13 @@ HBM_PEAK_GBS = 8000.0
 CHECK_EVERY = 1000
 
 
+def rel_residual(out):
+    """sqrt(sum |du|^2 / sum |u|^2); non-finite whenever a sum is (never 0 for NaN)."""
+    if out[1] > 0:
+        return (out[0] / out[1]) ** 0.5
+    return 0.0 if (out[1] == 0 and out[0] == 0) else math.inf
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -50,7 +57,7 @@ def run_gpu(w: workloads.Cavity, steps: int, warmup: int):
         done += n
         if done % CHECK_EVERY == 0:
             out = sol.residual()
-            R = (out[0] / out[1]) ** 0.5 if out[1] > 0 else 0.0
+            R = rel_residual(out)
             if diverged_at is None and not (math.isfinite(R) and out[3] < 1.0):
                 diverged_at = done
     torch.cuda.synchronize()
@@ -71,7 +78,7 @@ def run_gpu(w: workloads.Cavity, steps: int, warmup: int):
         done += n
         if done % CHECK_EVERY == 0:
             out = sol.residual()  # synchronises the stream
-            R = (out[0] / out[1]) ** 0.5 if out[1] > 0 else 0.0
+            R = rel_residual(out)
             hist.append(R)
             if diverged_at is None and not (math.isfinite(R) and out[3] < 1.0):
                 diverged_at = warmup + done
@@ -133,7 +140,7 @@ def pmc_run(steps: int):
         b.copy_(a)
     torch.cuda.synchronize()
     log(f"[pmc] 5 copies of {4 * n} bytes done")
-    for w in (workloads.CAVITY_1024x512_F32, workloads.CAVITY_4096x2048_F32):
+    for w in PMC_GRIDS:
         p = solver.make_params(w.nx, w.ny, w.r, w.gamma, re=w.re, u_lid=w.u_lid,
                                storage=STORAGE[w.storage])
         from paper_2208_03562_amd import capi
@@ -170,6 +177,54 @@ def oracle_parity(w: workloads.Cavity, wc: workloads.Cavity):
     return out
 
 
+PMC_COPY_BYTES = 256 * 2 ** 20  # bytes read and bytes written by pmc_run's copy
+PMC_GRIDS = (workloads.CAVITY_1024x512_F32, workloads.CAVITY_4096x2048_F32)
+
+
+def traffic_from_counters(pmc_dir: str):
+    """Write profiles/traffic.json from two rocprofv3 --pmc runs of
+    `bench.py --pmc-run N` (pmc_dir/FETCH_SIZE and pmc_dir/WRITE_SIZE, CSV
+    output named run_*).  Each counter is scaled by what it reads for the
+    256 MiB copy, then averaged over the sweep dispatches of each grid (the
+    kernel instance dispatched most often on that grid: the tuned tile)."""
+    import collections
+    import csv
+
+    from paper_2208_03562_amd import build
+
+    rec = {"source_hash": build.source_hash(), "copy_scale": {}, "kib_per_dispatch": {},
+           "note": "bytes per launch of k_sweep: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) "
+                   "each scaled by its reading for a 256 MiB device copy"}
+    per = {}
+    for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
+        rows = list(csv.DictReader(open(os.path.join(pmc_dir, ctr, "run_counter_collection.csv"))))
+        copy = [(int(r["Grid_Size"]), float(r["Counter_Value"])) for r in rows
+                if "copyBuffer" in r["Kernel_Name"] and r["Counter_Name"] == ctr]
+        big = max(g for g, _ in copy)
+        copy = [v for g, v in copy if g == big]
+        copy_kib = sum(copy) / len(copy)
+        scale = PMC_COPY_BYTES / (copy_kib * 1024.0)
+        rec["copy_scale"][ctr] = round(scale, 5)
+        for w in PMC_GRIDS:
+            groups = collections.defaultdict(list)
+            for r in rows:
+                if ("k_sweep" in r["Kernel_Name"] and r["Counter_Name"] == ctr
+                        and int(r["Grid_Size"]) == w.nx * w.ny):
+                    groups[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+            name, vals = max(groups.items(), key=lambda kv: len(kv[1]))
+            kib = sum(vals) / len(vals)
+            rec["kib_per_dispatch"].setdefault(w.name, {})[ctr] = round(kib, 3)
+            rec["kib_per_dispatch"][w.name]["kernel"] = name.split("(")[0].replace("void ", "")
+            rec["kib_per_dispatch"][w.name]["dispatches"] = len(vals)
+            per[w.name] = per.get(w.name, 0.0) + kib * 1024.0 * scale
+    for k, v in per.items():
+        rec[k] = int(round(v))
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec))
+
+
 def measured_traffic(w: workloads.Cavity):
     """HBM bytes per launch of the sweep from the committed counter summary,
     if it was taken on the current kernel sources (else None)."""
@@ -188,6 +243,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--pmc-run", type=int, default=0,
                     help="only run the short counter workload with this many sweeps per grid")
+    ap.add_argument("--traffic-from", default="",
+                    help="write profiles/traffic.json from the two counter runs in this folder")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=2000)
@@ -201,6 +258,9 @@ def main():
               "multi-GPU path in this library", file=sys.stderr)
         sys.exit(2)
 
+    if args.traffic_from:
+        traffic_from_counters(args.traffic_from)
+        return
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
@@ -214,10 +274,11 @@ def main():
     comp = run_gpu(wc, args.steps, args.warmup)
     big = {}
     if args.hbm_steps > 0:
-        for wh in (workloads.CAVITY_4096x2048_F32, workloads.CAVITY_4096x2048_MA006["f16"],
-                   workloads.CAVITY_4096x2048_MA006["bf16"]):
+        for wh in (workloads.CAVITY_4096x2048_F32, workloads.CAVITY_4096x2048_MA002["f32"],
+                   workloads.CAVITY_4096x2048_MA002["f16"],
+                   workloads.CAVITY_4096x2048_MA002["bf16"]):
             r = run_gpu(wh, args.hbm_steps, min(args.warmup, 500))
-            big[wh.storage] = dict(
+            big[wh.name] = dict(
                 workload=wh.name, u_lid=round(wh.u_lid, 6), mlups=round(r["mlups"], 1),
                 sweep_us=round(r["sweep_us"], 2), achieved_gbs=round(r["sweep_gbs"], 1),
                 frac=round(r["sweep_gbs"] / HBM_PEAK_GBS, 4),
@@ -245,7 +306,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(main_res["sweep_gbs"], 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(main_res["sweep_gbs"] / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "k_sweep",
+                     "traffic": traffic, "traffic_unit": "bytes per launch",
+                     "algorithmic_bytes": BYTES_PER_NODE[w.storage] * w.nx * w.ny,
+                     "kernel": "k_sweep",
                      "kernel_us": round(main_res["sweep_us"], 3),
                      "note": "72 B/node (9 FP32 reads + 9 FP32 writes) x 524288 nodes per launch; "
                              "the 37.7 MB working set stays in the last-level cache"},

@@ -592,8 +592,9 @@ int orc_solve(const orc_params *p, double *ft, double tol, int64_t check_every,
         n += check_every;
         double out[4];
         orc_residual(p, ft, uxp, uyp, out);
+        /* a NaN in either sum makes R non-finite (diverged), never 0 */
         double R = out[1] > 0.0 ? sqrt(out[0] / out[1])
-                                : (out[0] > 0.0 ? INFINITY : 0.0);
+                                : (out[1] == 0.0 && out[0] == 0.0 ? 0.0 : INFINITY);
         if (hist && nh < hist_cap) hist[nh] = R;
         ++nh;
         if (!isfinite(R) || !isfinite(out[2]) || !(out[3] < 1.0)) {

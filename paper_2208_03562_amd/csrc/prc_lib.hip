@@ -603,7 +603,9 @@ prc_status prc_solve(const prc_params *p, void *f_a, void *f_b, double *u_prev, 
         n += check_every;
         void *now = (n & 1) ? f_b : f_a;
         if ((st = prc_residual(p, now, u_prev, scratch, out, stream)) != PRC_OK) return st;
-        const double R = out[1] > 0.0 ? std::sqrt(out[0] / out[1]) : (out[0] > 0.0 ? INFINITY : 0.0);
+        // a NaN in either sum makes R non-finite (diverged), never 0
+        const double R = out[1] > 0.0 ? std::sqrt(out[0] / out[1])
+                                      : (out[1] == 0.0 && out[0] == 0.0 ? 0.0 : INFINITY);
         if (hist && nh < hist_cap) hist[nh] = R;
         ++nh;
         if (!std::isfinite(R) || !std::isfinite(out[2]) || !(out[3] < 1.0)) {

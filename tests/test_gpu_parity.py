@@ -134,19 +134,27 @@ def test_cavity_64x32_f64_trajectory_and_convergence(O, torch_cuda):
     assert max_rel_velocity_error(ux, uy, oux, ouy, w.u_lid) < 1e-11
 
 
+# Relative residual reached by each storage.  FP32 deviations and arithmetic
+# leave a rounding floor near 1e-7 in the 500-step relative residual of this
+# cavity (the change of u between checks is then mostly rounding), so the
+# FP32 solve stops at 1e-6, where the residual is still the flow's own decay.
+REDUCED_TOL = {"f64": 1e-7, "f32": 1e-6}
+
+
 @pytest.mark.parametrize("storage", ["f32", "f64"])
 def test_cavity_reduced_grid_solve(O, torch_cuda, storage):
     """A small cavity at gamma = 0.1, r = 2 and Ma = 0.06 (the lid speed the
     paper pairs with gamma = 0.1 in Sec. 5): the whole solve to a residual of
-    1e-7 agrees with the oracle in steps (within 1 %) and in the velocity
-    field (1e-5 of U)."""
+    1e-7 (FP64) or 1e-6 (FP32) agrees with the oracle in steps (within 1 %)
+    and in the velocity field (1e-5 of U)."""
     U = workloads.MA006_LID
+    tol = REDUCED_TOL[storage]
     s = spec(64, 32, 2.0, 0.1, omega_nu=None, re=62.5, u_lid=U, storage=storage)
     po = oracle_params(O, s)
     sol = make_solver(s)
-    st, n, hist = sol.solve(1e-7, 500, 100000)
+    st, n, hist = sol.solve(tol, 500, 100000)
     ft = O.rest_state(po)
-    ost, on, ohist = O.solve(po, ft, 1e-7, 500, 100000)
+    ost, on, ohist = O.solve(po, ft, tol, 500, 100000)
     assert st == 0 and ost == 0
     assert abs(n - on) <= 0.01 * on, (n, on)
     _, ux, uy = (a.cpu().numpy() for a in sol.macros())
