@@ -225,6 +225,28 @@ def traffic_from_counters(pmc_dir: str):
     print(json.dumps(rec))
 
 
+def trace_summary(trace_dir: str):
+    """Markdown table of a rocprofv3 --kernel-trace run of bench.py (CSV output
+    named bench_*): dispatches, mean, median and minimum duration per kernel
+    instance and grid size (the library's --stats table merges grids)."""
+    import collections
+    import csv
+    import statistics
+
+    rows = csv.DictReader(open(os.path.join(trace_dir, "bench_kernel_trace.csv")))
+    groups = collections.defaultdict(list)
+    for r in rows:
+        name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+        groups[(name, int(r["Grid_Size_X"]))].append(
+            int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    print("| kernel | grid (threads) | dispatches | mean us | median us | min us |")
+    print("|---|---|---|---|---|---|")
+    for (name, grid), v in sorted(groups.items(), key=lambda kv: -sum(kv[1])):
+        v = sorted(v)
+        print(f"| `{name}` | {grid} | {len(v)} | {statistics.mean(v) / 1e3:.3f} | "
+              f"{v[len(v) // 2] / 1e3:.3f} | {v[0] / 1e3:.3f} |")
+
+
 def measured_traffic(w: workloads.Cavity):
     """HBM bytes per launch of the sweep from the committed counter summary,
     if it was taken on the current kernel sources (else None)."""
@@ -245,6 +267,8 @@ def main():
                     help="only run the short counter workload with this many sweeps per grid")
     ap.add_argument("--traffic-from", default="",
                     help="write profiles/traffic.json from the two counter runs in this folder")
+    ap.add_argument("--trace-summary", default="",
+                    help="print per-grid kernel durations of a kernel-trace run in this folder")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=2000)
@@ -258,6 +282,9 @@ def main():
               "multi-GPU path in this library", file=sys.stderr)
         sys.exit(2)
 
+    if args.trace_summary:
+        trace_summary(args.trace_summary)
+        return
     if args.traffic_from:
         traffic_from_counters(args.traffic_from)
         return
