@@ -194,6 +194,94 @@ prc_status prc_set_tile(const prc_params *p, int32_t tile);
 /* Drop the launch graphs cached by prc_step (they hold no user memory). */
 prc_status prc_release_graphs(void);
 
+/* ---- Batches: many independent problems advanced together -------------
+ *
+ * The collision and streaming of Appendix A are local to a node and its
+ * neighbours, so problems of different sizes and parameters (grid, r, gamma,
+ * Re, lid) can share one launch per time step: a batch keeps a list of the
+ * tiles of all its members and sweeps them together, which fills the GPU
+ * with problems far too small to fill it alone.  Every member gets exactly
+ * the arithmetic of prc_step / prc_residual / prc_solve on its own: its
+ * states and residuals are bit for bit those of the same problem run alone.
+ *
+ * All members of a batch share one storage type and one boundary type.  A
+ * member's state buffers, u_prev and their memory stay owned by the caller
+ * and must stay valid while it is a member.  Between calls the newest state
+ * of every member is in its f_a (all steps are taken in even numbers).
+ * The batch object owns small device tables (tile and reduction lists) and
+ * launch graphs, allocated on first use and freed by prc_batch_destroy.
+ * A batch is not thread safe: one thread and one stream at a time.
+ */
+typedef struct prc_batch prc_batch;
+
+/* Status of a member after prc_batch_solve. */
+typedef enum {
+    PRC_MEMBER_ACTIVE = 2,      /* still being advanced */
+    PRC_MEMBER_CONVERGED = 0,   /* relative residual fell below tol */
+    PRC_MEMBER_MAX_STEPS = 1,   /* step limit reached without converging */
+    PRC_MEMBER_DIVERGED = -3,   /* non-finite residual or mass, or max |u| >= 1 */
+    PRC_MEMBER_REMOVED = -5     /* taken out by prc_batch_remove */
+} prc_member_status;
+
+/* Create an empty batch for problems with this storage (prc_storage) and
+ * boundary type (prc_bc).  Host only. */
+prc_status prc_batch_create(int32_t storage, int32_t bc, prc_batch **out);
+
+/* Free the batch's own tables and graphs (not the members' buffers).
+ * Synchronises the device if anything was allocated.  NULL is a no-op. */
+prc_status prc_batch_destroy(prc_batch *b);
+
+/* Add a problem.  p must pass prc_validate and match the batch's storage and
+ * boundary type.  f_a (holding the current state), f_b: distinct device
+ * buffers of prc_state_bytes(p), 256-byte aligned; u_prev: device
+ * double[2][ny][nx].  The member joins the next prc_batch_step or
+ * prc_batch_solve; prc_batch_solve first takes its velocity snapshot, as
+ * prc_solve does.  *id_out receives the member's id: 0, 1, 2, ... in order
+ * of addition, never reused.  Host only. */
+prc_status prc_batch_add(prc_batch *b, const prc_params *p, void *f_a, void *f_b,
+                         double *u_prev, int32_t *id_out);
+
+/* Take member id out of the batch (its buffers are no longer touched by
+ * later calls).  Host only. */
+prc_status prc_batch_remove(prc_batch *b, int32_t id);
+
+/* Number of members added so far (ids 0 .. n-1) and of active members. */
+prc_status prc_batch_count(const prc_batch *b, int32_t *n_added, int32_t *n_active);
+
+/* Advance every active member by nsteps (even, >= 0) time steps: one sweep
+ * launch per step and variant (members with every correction and no body
+ * force, and the others) covers all of their tiles.  Long runs replay
+ * captured graphs.  Asynchronous on stream. */
+prc_status prc_batch_step(prc_batch *b, int64_t nsteps, hipStream_t stream);
+
+/* Convergence check of every active member, as prc_residual (same sums, same
+ * order, same update of u_prev): out[4 * id + k] for each active id (host,
+ * double[4 * n_added]; other entries untouched).  Synchronises the stream. */
+prc_status prc_batch_residual(prc_batch *b, double *out, hipStream_t stream);
+
+/* Solve every active member as prc_solve would, side by side: snapshot the
+ * velocity of members that have none yet, then repeat { advance all active
+ * members check_every (even) steps; check all }; after each check a member
+ * leaves the batch as CONVERGED (relative residual < tol), DIVERGED, or
+ * MAX_STEPS once it has taken max_steps (a multiple of check_every) steps.
+ * Returns when no member is active.  Per id (host arrays of n_added
+ * entries, any may be NULL): status (prc_member_status), steps (taken by the
+ * member since it joined), hist[id * hist_cap + k] (relative residual of its
+ * k-th check) and hist_len.  The newest state of each member is in its f_a.
+ * Returns PRC_OK when every member has left, or an error. */
+prc_status prc_batch_solve(prc_batch *b, double tol, int64_t check_every, int64_t max_steps,
+                           int32_t *status, int64_t *steps, double *hist, int64_t hist_cap,
+                           int64_t *hist_len, hipStream_t stream);
+
+/* Autotuner for the batch sweep: time each tile shape (indices as for
+ * prc_tune) on the current members, sweeping f_a into f_b (f_a, which holds
+ * the state, is only read), and keep the fastest for this batch.  tile_out
+ * (may be NULL) receives it.  Synchronises the stream. */
+prc_status prc_batch_tune(prc_batch *b, int32_t *tile_out, hipStream_t stream);
+
+/* Use tile shape `tile` (0, 1, 2) for this batch's sweeps.  Host only. */
+prc_status prc_batch_set_tile(prc_batch *b, int32_t tile);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *prc_last_error(void);
 

@@ -8,14 +8,19 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libprc.so")
-SOURCES = [os.path.join(CSRC, "prc_lib.hip")]
+SOURCES = [os.path.join(CSRC, "prc_lib.hip"), os.path.join(CSRC, "prc_batch.hip")]
 HEADERS = [os.path.join(CSRC, h) for h in ("prc_coef.hpp", "prc_device.hpp", "prc_collide.hpp",
-                                         "prc_sweep.hpp")] + [
+                                         "prc_sweep.hpp", "prc_host.hpp", "prc_reduce.hpp")] + [
     os.path.join(ROOT, "include", "prc.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # multiply-adds are fused only within one source expression, so a node's
+    # arithmetic is fixed by the source alone: the single-problem and the
+    # batched sweeps, which inline the same code into different kernels,
+    # give the same bits
+    "-ffp-contract=on",
     # no packed FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",

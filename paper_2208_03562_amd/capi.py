@@ -28,6 +28,9 @@ STORAGE_BYTES = {PRC_F64: 8, PRC_F32: 4, PRC_F16: 2, PRC_BF16: 2}
 PRC_CORR_THETA, PRC_CORR_LAMBDA, PRC_CORR_K11, PRC_CORR_ALL = 1, 2, 4, 7
 # prc_frame
 PRC_FRAME_CENTRAL, PRC_FRAME_RAW = 0, 1
+# prc_member_status
+PRC_MEMBER_ACTIVE, PRC_MEMBER_CONVERGED, PRC_MEMBER_MAX_STEPS = 2, 0, 1
+PRC_MEMBER_DIVERGED, PRC_MEMBER_REMOVED = -3, -5
 
 
 class prc_params(ctypes.Structure):
@@ -79,6 +82,20 @@ _PROTOS = {
     "prc_set_tile": (ctypes.c_int, [_P, ctypes.c_int32]),
     "prc_release_graphs": (ctypes.c_int, []),
     "prc_last_error": (ctypes.c_char_p, []),
+    "prc_batch_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_VP)]),
+    "prc_batch_destroy": (ctypes.c_int, [_VP]),
+    "prc_batch_add": (ctypes.c_int, [_VP, _P, _VP, _VP, _VP, ctypes.POINTER(ctypes.c_int32)]),
+    "prc_batch_remove": (ctypes.c_int, [_VP, ctypes.c_int32]),
+    "prc_batch_count": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32)]),
+    "prc_batch_step": (ctypes.c_int, [_VP, ctypes.c_int64, _VP]),
+    "prc_batch_residual": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double), _VP]),
+    "prc_batch_solve": (ctypes.c_int, [_VP, ctypes.c_double, ctypes.c_int64, ctypes.c_int64,
+                                       ctypes.POINTER(ctypes.c_int32), _I64P,
+                                       ctypes.POINTER(ctypes.c_double), ctypes.c_int64, _I64P,
+                                       _VP]),
+    "prc_batch_tune": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int32), _VP]),
+    "prc_batch_set_tile": (ctypes.c_int, [_VP, ctypes.c_int32]),
 }
 
 _lib = None
@@ -202,3 +219,73 @@ def prc_tune(p: prc_params, stream: int = 0) -> int:
 
 def prc_set_tile(p: prc_params, tile: int) -> None:
     _check("prc_set_tile", lib().prc_set_tile(ctypes.byref(p), int(tile)))
+
+
+# ---- batches ---------------------------------------------------------------
+
+def prc_batch_create(storage: int, bc: int) -> int:
+    """Returns the opaque batch handle (an integer)."""
+    h = _VP()
+    _check("prc_batch_create", lib().prc_batch_create(int(storage), int(bc), ctypes.byref(h)))
+    return h.value
+
+
+def prc_batch_destroy(b: int) -> None:
+    _check("prc_batch_destroy", lib().prc_batch_destroy(b))
+
+
+def prc_batch_add(b: int, p: prc_params, f_a: int, f_b: int, u_prev: int) -> int:
+    i = ctypes.c_int32(-1)
+    _check("prc_batch_add", lib().prc_batch_add(b, ctypes.byref(p), f_a, f_b, u_prev,
+                                                ctypes.byref(i)))
+    return i.value
+
+
+def prc_batch_remove(b: int, member: int) -> None:
+    _check("prc_batch_remove", lib().prc_batch_remove(b, int(member)))
+
+
+def prc_batch_count(b: int):
+    """(members added, members active)."""
+    n, a = ctypes.c_int32(), ctypes.c_int32()
+    _check("prc_batch_count", lib().prc_batch_count(b, ctypes.byref(n), ctypes.byref(a)))
+    return n.value, a.value
+
+
+def prc_batch_step(b: int, nsteps: int, stream: int = 0) -> None:
+    _check("prc_batch_step", lib().prc_batch_step(b, int(nsteps), stream))
+
+
+def prc_batch_residual(b: int, stream: int = 0):
+    """{id: [N, D, mass, max |u|^2]} for the active members."""
+    n, _ = prc_batch_count(b)
+    out = (ctypes.c_double * max(1, 4 * n))(*([float("nan")] * max(1, 4 * n)))
+    _check("prc_batch_residual", lib().prc_batch_residual(b, out, stream))
+    return out
+
+
+def prc_batch_solve(b: int, tol: float, check_every: int, max_steps: int, hist_cap: int = 0,
+                    stream: int = 0):
+    """Returns (status[id], steps[id], hist[id] lists) for every member added."""
+    n, _ = prc_batch_count(b)
+    m = max(1, n)
+    status = (ctypes.c_int32 * m)()
+    steps = (ctypes.c_int64 * m)()
+    hl = (ctypes.c_int64 * m)()
+    hist = (ctypes.c_double * max(1, m * hist_cap))() if hist_cap > 0 else None
+    _check("prc_batch_solve", lib().prc_batch_solve(b, float(tol), int(check_every),
+                                                    int(max_steps), status, steps, hist,
+                                                    int(hist_cap), hl, stream))
+    hists = [list(hist[i * hist_cap: i * hist_cap + min(hl[i], hist_cap)]) if hist else []
+             for i in range(n)]
+    return list(status[:n]), list(steps[:n]), hists
+
+
+def prc_batch_tune(b: int, stream: int = 0) -> int:
+    t = ctypes.c_int32(-1)
+    _check("prc_batch_tune", lib().prc_batch_tune(b, ctypes.byref(t), stream))
+    return t.value
+
+
+def prc_batch_set_tile(b: int, tile: int) -> None:
+    _check("prc_batch_set_tile", lib().prc_batch_set_tile(b, int(tile)))

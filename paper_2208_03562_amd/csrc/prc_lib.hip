@@ -13,6 +13,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -22,135 +23,11 @@
 #include "prc.h"
 #include "prc_coef.hpp"
 #include "prc_device.hpp"
+#include "prc_host.hpp"
+#include "prc_reduce.hpp"
 #include "prc_sweep.hpp"
 
 namespace prc {
-
-// ---------------------------------------------------------------- errors --
-static thread_local std::string g_err;
-
-static prc_status fail(prc_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
-static prc_status fail(prc_status s, const char *fmt, ...)
-{
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_err = buf;
-    return s;
-}
-
-#define HIP_TRY(expr)                                                                    \
-    do {                                                                                 \
-        hipError_t e_ = (expr);                                                          \
-        if (e_ != hipSuccess)                                                            \
-            return fail(PRC_EHIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_),         \
-                        __FILE__, __LINE__);                                             \
-    } while (0)
-
-// ---------------------------------------------------------------- layout --
-constexpr int kPitchAlignBytes = 256;
-constexpr int kRedBlock = 256;
-constexpr int kRedMaxBlocks = 1024;
-
-static size_t elem_bytes(int storage)
-{
-    switch (storage) {
-    case PRC_F64: return 8;
-    case PRC_F32: return 4;
-    default: return 2;
-    }
-}
-
-// State layouts (element (a, j, i) at a * plane + j * row + i):
-//   0  plane-major: nine whole planes one after the other
-//   1  plane-major with each plane padded by kPlanePadBytes, so that the nine
-//      loads of a node do not all fall on addresses a power of two apart
-//   2  row-interleaved: row j of all nine planes stored together
-//      ([j][a][i]), so a tile's loads and stores stay within a few DRAM pages
-constexpr int kLayoutDefault = 2;
-constexpr int64_t kPlanePadBytes = 4096 + 256;
-
-static int layout_mode()
-{
-    static const int v = [] {
-        const char *e = std::getenv("PRC_LAYOUT");
-        const int m = e ? std::atoi(e) : kLayoutDefault;
-        return (m >= 0 && m <= 2) ? m : kLayoutDefault;
-    }();
-    return v;
-}
-
-// row and plane strides and total size, in elements
-static void layout(const prc_params &p, int64_t &row, int64_t &plane, int64_t &total)
-{
-    const int64_t E = (int64_t)elem_bytes(p.storage);
-    const int64_t per = kPitchAlignBytes / E;
-    const int64_t pitch = ((int64_t)p.nx + per - 1) / per * per;
-    switch (layout_mode()) {
-    case 1:
-        row = pitch;
-        plane = pitch * p.ny + kPlanePadBytes / E;
-        total = 9 * plane;
-        break;
-    case 2:
-        row = 9 * pitch;
-        plane = pitch;
-        total = row * p.ny;
-        break;
-    default:
-        row = pitch;
-        plane = pitch * p.ny;
-        total = 9 * plane;
-    }
-}
-
-static prc_status validate(const prc_params *p)
-{
-    if (!p) return fail(PRC_EINVAL, "params is NULL");
-    if (p->nx < 3 || p->ny < 3) return fail(PRC_EINVAL, "nx, ny must be >= 3 (got %d, %d)", p->nx, p->ny);
-    if ((int64_t)p->nx * p->ny > ((int64_t)1 << 30))
-        return fail(PRC_EINVAL, "grid too large (%d x %d)", p->nx, p->ny);
-    if (!(p->r > 0.0) || !std::isfinite(p->r)) return fail(PRC_EINVAL, "r must be > 0");
-    if (!(p->gamma > 0.0 && p->gamma <= 1.0)) return fail(PRC_EINVAL, "gamma must be in (0, 1]");
-    const double om[5] = {p->omega_nu, p->omega_xi, p->omega_1, p->omega_3, p->omega_4};
-    for (double w : om)
-        if (!(w > 0.0 && w < 2.0)) return fail(PRC_EINVAL, "relaxation rates must be in (0, 2)");
-    const double q = p->r < 1.0 ? p->r : 1.0;
-    if (!(std::fabs(p->u_lid) < q / std::sqrt(3.0)))
-        return fail(PRC_EINVAL, "|u_lid| must be below the sound speed q/sqrt(3)");
-    if (!std::isfinite(p->fx) || !std::isfinite(p->fy)) return fail(PRC_EINVAL, "force not finite");
-    if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) return fail(PRC_EINVAL, "rho0 must be > 0");
-    if (p->bc < PRC_BC_CAVITY || p->bc > PRC_BC_CHANNEL) return fail(PRC_EINVAL, "unknown bc %d", p->bc);
-    if (p->storage < PRC_F64 || p->storage > PRC_BF16)
-        return fail(PRC_EINVAL, "unknown storage %d", p->storage);
-    if (p->corrections < 0 || p->corrections > PRC_CORR_ALL)
-        return fail(PRC_EINVAL, "corrections bitmask out of range");
-    if (p->frame != PRC_FRAME_CENTRAL)
-        return fail(PRC_EINVAL, "frame %d is not available in this library", p->frame);
-    int64_t row, plane, total;
-    layout(*p, row, plane, total);
-    // byte offsets into one state buffer are 32-bit (buffer addressing)
-    if (total * (int64_t)elem_bytes(p->storage) > (int64_t)0xFFFFFFFF)
-        return fail(PRC_EINVAL, "state of %d x %d exceeds 4 GiB", p->nx, p->ny);
-    return PRC_OK;
-}
-
-static prc_status check_buf(const void *b, const char *name)
-{
-    if (!b) return fail(PRC_EINVAL, "%s is NULL", name);
-    if ((uintptr_t)b % 256 != 0) return fail(PRC_EINVAL, "%s is not 256-byte aligned", name);
-    return PRC_OK;
-}
-
-template <typename ST>
-static Coef<typename Mem<ST>::CT> coef_of(const prc_params &p)
-{
-    int64_t row, plane, total;
-    layout(p, row, plane, total);
-    return make_coef<typename Mem<ST>::CT>(p, row, plane, total, (int64_t)sizeof(ST));
-}
 
 // ------------------------------------------------------------- kernels --
 
@@ -171,83 +48,14 @@ __global__ void k_macros(const ST *__restrict__ f, const Coef<typename Mem<ST>::
     if (uy) uy[n] = (double)v;
 }
 
-// block-wide fixed-order sum of four doubles (and a max in slot 3)
-__device__ __forceinline__ void block_reduce4(double v[4], double *sh /* [4][kRedBlock] */)
+
+// zero fill of n 16-byte words (grid-stride)
+__global__ void k_zero(uint4 *__restrict__ p, size_t n)
 {
-    const int t = threadIdx.x;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) sh[k * kRedBlock + t] = v[k];
-    __syncthreads();
-    for (int s = kRedBlock / 2; s > 0; s >>= 1) {
-        if (t < s) {
-#pragma unroll
-            for (int k = 0; k < 3; ++k) sh[k * kRedBlock + t] += sh[k * kRedBlock + t + s];
-            const double a = sh[3 * kRedBlock + t], b = sh[3 * kRedBlock + t + s];
-            sh[3 * kRedBlock + t] = (a >= b || a != a) ? a : b;  // NaN sticks
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) v[k] = sh[k * kRedBlock];
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = make_uint4(0u, 0u, 0u, 0u);
 }
-
-template <typename ST, int BC>
-__global__ void __launch_bounds__(kRedBlock)
-    k_residual(const ST *__restrict__ f, const Coef<typename Mem<ST>::CT> c,
-               double *__restrict__ u_prev, double *__restrict__ partial)
-{
-    using CT = typename Mem<ST>::CT;
-    __shared__ double sh[4 * kRedBlock];
-    const int64_t N = (int64_t)c.nx * c.ny;
-    const rsrc_t rs = make_rsrc(f, c.state_bytes);
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t n = (int64_t)blockIdx.x * kRedBlock + threadIdx.x; n < N;
-         n += (int64_t)gridDim.x * kRedBlock) {
-        const int x = (int)(n % c.nx), y = (int)(n / c.nx);
-        CT d[9];
-        pull_checked<ST, BC>(c, rs, x, y, d);
-        CT drho, u, v;
-        fields(c, d, drho, u, v);
-        const double du = (double)u - u_prev[n], dv = (double)v - u_prev[N + n];
-        const double u2 = (double)u * (double)u + (double)v * (double)v;
-        acc[0] += du * du + dv * dv;
-        acc[1] += u2;
-        acc[2] += (double)drho;
-        if (!(u2 <= acc[3])) acc[3] = u2;
-        u_prev[n] = (double)u;
-        u_prev[N + n] = (double)v;
-    }
-    block_reduce4(acc, sh);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) partial[4 * blockIdx.x + k] = acc[k];
-    }
-}
-
-__global__ void __launch_bounds__(kRedBlock)
-    k_finish(const double *__restrict__ partial, int nblocks, double *__restrict__ out)
-{
-    __shared__ double sh[4 * kRedBlock];
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int b = threadIdx.x; b < nblocks; b += kRedBlock) {
-        for (int k = 0; k < 3; ++k) acc[k] += partial[4 * b + k];
-        const double m = partial[4 * b + 3];
-        if (!(m <= acc[3])) acc[3] = m;
-    }
-    block_reduce4(acc, sh);
-    if (threadIdx.x == 0)
-        for (int k = 0; k < 4; ++k) out[k] = acc[k];
-}
-
-// ------------------------------------------------------------ dispatch --
-
-// Sweep tile shapes (threads along x, along y).  A taller tile needs fewer
-// ring densities per node; a wider one gives longer contiguous row segments.
-struct TileShape {
-    int tx, ty;
-};
-constexpr TileShape kTiles[] = {{64, 4}, {64, 8}, {128, 4}};
-constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
 // Tile shape per problem: what prc_tune measured for this grid, else a
 // default (wide tiles for wide grids); PRC_TILE=<index> forces one shape.
@@ -331,13 +139,6 @@ static prc_status launch_macros(const prc_params &p, const void *f, double *rho,
     return PRC_OK;
 }
 
-static int red_blocks(const prc_params &p)
-{
-    const int64_t N = (int64_t)p.nx * p.ny;
-    int64_t b = (N + kRedBlock - 1) / kRedBlock;
-    return (int)(b < kRedMaxBlocks ? b : kRedMaxBlocks);
-}
-
 template <typename ST, int BC>
 static prc_status launch_residual(const prc_params &p, const void *f, double *u_prev,
                                   double *scratch, hipStream_t s)
@@ -347,36 +148,15 @@ static prc_status launch_residual(const prc_params &p, const void *f, double *u_
     hipLaunchKernelGGL((k_residual<ST, BC>), dim3(nb), dim3(kRedBlock), 0, s, (const ST *)f, c,
                        u_prev, scratch);
     HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kRedBlock), 0, s, (const double *)scratch, nb,
+    hipLaunchKernelGGL(k_finish<>, dim3(1), dim3(kRedBlock), 0, s, (const double *)scratch, nb,
                        scratch + 4 * kRedMaxBlocks);
     HIP_TRY(hipGetLastError());
     return PRC_OK;
 }
 
-// run F<ST, BC>(args...) for the storage and boundary type of p
-#define PRC_DISPATCH(p, FN, ...)                                                          \
-    [&]() -> prc_status {                                                                \
-        switch ((p).storage * 3 + (p).bc) {                                              \
-        case PRC_F64 * 3 + 0: return FN<double, 0>(__VA_ARGS__);                         \
-        case PRC_F64 * 3 + 1: return FN<double, 1>(__VA_ARGS__);                         \
-        case PRC_F64 * 3 + 2: return FN<double, 2>(__VA_ARGS__);                         \
-        case PRC_F32 * 3 + 0: return FN<float, 0>(__VA_ARGS__);                          \
-        case PRC_F32 * 3 + 1: return FN<float, 1>(__VA_ARGS__);                          \
-        case PRC_F32 * 3 + 2: return FN<float, 2>(__VA_ARGS__);                          \
-        case PRC_F16 * 3 + 0: return FN<__half, 0>(__VA_ARGS__);                         \
-        case PRC_F16 * 3 + 1: return FN<__half, 1>(__VA_ARGS__);                         \
-        case PRC_F16 * 3 + 2: return FN<__half, 2>(__VA_ARGS__);                         \
-        case PRC_BF16 * 3 + 0: return FN<__hip_bfloat16, 0>(__VA_ARGS__);                \
-        case PRC_BF16 * 3 + 1: return FN<__hip_bfloat16, 1>(__VA_ARGS__);                \
-        case PRC_BF16 * 3 + 2: return FN<__hip_bfloat16, 2>(__VA_ARGS__);                \
-        }                                                                                \
-        return fail(PRC_EINVAL, "bad storage/bc");                                       \
-    }()
-
 // --------------------------------------------------------- launch graphs --
 // prc_step replays captured graphs of sweeps for long runs: one graph per
 // (device, problem, buffer pair), cached until prc_release_graphs().
-constexpr int kGraphStepsDefault = 64;  // even
 constexpr size_t kGraphCacheMax = 32;
 
 static_assert(sizeof(prc_params) == 8 + 11 * 8 + 4 * 4, "prc_params has no padding");
@@ -387,18 +167,6 @@ struct GraphEntry {
 };
 static std::mutex g_graph_mu;
 static std::unordered_map<std::string, GraphEntry> g_graphs;
-
-// sweeps per graph; PRC_GRAPH_STEPS overrides (0 disables graphs)
-static int graph_steps()
-{
-    static const int v = [] {
-        const char *e = std::getenv("PRC_GRAPH_STEPS");
-        if (!e) return kGraphStepsDefault;
-        const int n = std::atoi(e);
-        return n <= 0 ? 0 : (n + 1) / 2 * 2;
-    }();
-    return v;
-}
 
 static void destroy_graphs_locked()
 {
@@ -524,8 +292,12 @@ prc_status prc_init(const prc_params *p, void *f, hipStream_t stream)
     prc_status st = validate(p);
     if (st != PRC_OK) return st;
     if ((st = check_buf(f, "f")) != PRC_OK) return st;
-    // all-zero bits are +0 in every storage type
-    HIP_TRY(hipMemsetAsync(f, 0, prc_state_bytes(p), stream));
+    // all-zero bits are +0 in every storage type; a kernel rather than a
+    // memset node, so that the call can be captured into a graph
+    const size_t words = prc_state_bytes(p) / sizeof(uint4);  // a multiple of 256 B
+    const unsigned blocks = (unsigned)std::min<size_t>((words + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, stream, (uint4 *)f, words);
+    HIP_TRY(hipGetLastError());
     return PRC_OK;
 }
 
@@ -695,6 +467,6 @@ prc_status prc_release_graphs(void)
     return PRC_OK;
 }
 
-const char *prc_last_error(void) { return g_err.c_str(); }
+const char *prc_last_error(void) { return err_slot().c_str(); }
 
 }  // extern "C"

@@ -7,7 +7,8 @@
 // densities go to an LDS tile, one barrier, then each thread computes the
 // gradient, collides and stores its node.
 //
-// k_sweep      one tile per workgroup (the grid covers all tiles once)
+// k_sweep        one tile per workgroup (the grid covers all tiles once)
+// k_sweep_batch  the same over a list of tiles of many independent problems
 #pragma once
 
 #include "prc_collide.hpp"
@@ -116,6 +117,46 @@ __global__ void __launch_bounds__(TX *TY)
     tile_densities<CT>(srho, g, d, e);
     __syncthreads();
     tile_finish<ST, TX, TY, FORCE, ALL>(c, make_rsrc(dst, c.state_bytes), srho, g, x0, y0, d);
+}
+
+// ---- batches ---------------------------------------------------------------
+// One member of a batch: its per-launch constants and its two state buffers.
+template <typename CT>
+struct BatchMember {
+    Coef<CT> c;
+    const void *buf[2];  // buf[parity] is read, buf[parity ^ 1] written
+    double *u_prev;      // velocity snapshot of the convergence check
+};
+
+// One tile of a member: its top-left node.
+struct BatchTile {
+    int32_t member, x0, y0, pad;
+};
+
+// One sweep over the tiles of many members.  The tile list is ordered member
+// by member; workgroup i runs on XCD i mod 8 and the list is split into eight
+// contiguous bands, so each member's tiles (and the halos they share) stay
+// within one or two XCDs' L2.  Member constants are read through the scalar
+// cache (the member index is uniform over the workgroup).
+template <typename ST, int BC, int TX, int TY, bool FORCE, bool ALL>
+__global__ void __launch_bounds__(TX *TY)
+    k_sweep_batch(const BatchTile *__restrict__ tiles, int ntiles, int tiles_per_xcd,
+                  const BatchMember<typename Mem<ST>::CT> *__restrict__ members, int parity)
+{
+    using CT = typename Mem<ST>::CT;
+    __shared__ CT srho[TY + 2][TX + 2];
+    const int t = (blockIdx.x % kXcds) * tiles_per_xcd + blockIdx.x / kXcds;
+    if (t >= ntiles) return;
+    const BatchTile tl = tiles[t];
+    const BatchMember<CT> &m = members[tl.member];
+    const Coef<CT> &c = m.c;
+    const TileGeom<TX, TY> g(threadIdx.x);
+    CT d[9], e[9];
+    tile_load<ST, BC>(c, make_rsrc(m.buf[parity], c.state_bytes), g, tl.x0, tl.y0, d, e);
+    tile_densities<CT>(srho, g, d, e);
+    __syncthreads();
+    tile_finish<ST, TX, TY, FORCE, ALL>(c, make_rsrc(m.buf[parity ^ 1], c.state_bytes), srho, g,
+                                        tl.x0, tl.y0, d);
 }
 
 }  // namespace prc

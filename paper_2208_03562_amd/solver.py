@@ -112,3 +112,83 @@ class Solver:
                                      hist_cap=max(1, max_steps // check_every + 1), stream=self.s)
         self.steps += n
         return st, n, hist
+
+
+class Batch:
+    """Many problems advanced side by side by shared launches (prc_batch_*).
+
+    Each member is a :class:`Solver` (it owns the member's buffers); the
+    batch holds the library's batch object.  All members share one storage
+    type, one boundary type and the batch's stream."""
+
+    def __init__(self, storage=capi.PRC_F32, bc=capi.PRC_BC_CAVITY, device="cuda:0",
+                 stream: torch.cuda.Stream | None = None):
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.handle = capi.prc_batch_create(storage, bc)
+        self.members: list[Solver] = []
+        self.active: list[bool] = []
+        self._joined_at: list[int] = []
+
+    @property
+    def s(self) -> int:
+        return self.stream.cuda_stream
+
+    def add(self, p: prc_params) -> int:
+        """Allocate a problem at rest and add it; returns its id."""
+        return self.add_solver(Solver(p, device=self.device, stream=self.stream))
+
+    def add_solver(self, sol: Solver) -> int:
+        """Add an existing problem (its newest state must be in its first buffer)."""
+        assert sol.steps % 2 == 0, "the newest state must be in f_a"
+        i = capi.prc_batch_add(self.handle, sol.p, sol.fa.data_ptr(), sol.fb.data_ptr(),
+                               sol.u_prev.data_ptr())
+        assert i == len(self.members)
+        self.members.append(sol)
+        self.active.append(True)
+        self._joined_at.append(sol.steps)
+        return i
+
+    def active_ids(self):
+        return [i for i, a in enumerate(self.active) if a]
+
+    def remove(self, i: int) -> None:
+        capi.prc_batch_remove(self.handle, i)
+        self.active[i] = False
+
+    def step(self, n: int) -> None:
+        capi.prc_batch_step(self.handle, n, self.s)
+        for i in self.active_ids():
+            self.members[i].steps += int(n)
+
+    def residual(self):
+        """{id: [N, D, mass, max |u|^2]} of the active members."""
+        out = capi.prc_batch_residual(self.handle, self.s)
+        return {i: list(out[4 * i: 4 * i + 4]) for i in self.active_ids()}
+
+    def solve(self, tol: float, check_every: int, max_steps: int, hist_cap: int = 0):
+        """prc_batch_solve; returns (status, steps since joining, histories) per id."""
+        status, steps, hists = capi.prc_batch_solve(self.handle, tol, check_every, max_steps,
+                                                    hist_cap=hist_cap, stream=self.s)
+        for i, m in enumerate(self.members):
+            if self.active[i]:
+                m.steps = self._joined_at[i] + steps[i]  # even: newest state in f_a
+                self.active[i] = status[i] == capi.PRC_MEMBER_ACTIVE
+        return status, steps, hists
+
+    def tune(self) -> int:
+        return capi.prc_batch_tune(self.handle, self.s)
+
+    def set_tile(self, tile: int) -> None:
+        capi.prc_batch_set_tile(self.handle, tile)
+
+    def close(self) -> None:
+        if self.handle:
+            capi.prc_batch_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

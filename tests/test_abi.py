@@ -114,3 +114,56 @@ def test_set_tile_validates_without_gpu():
     capi.prc_set_tile(p, -1)
     with pytest.raises(capi.PrcError):
         capi.prc_set_tile(p, 7)
+
+
+# ---- batches: host-side argument checks (nothing is launched) -------------
+
+def test_batch_host_checks():
+    b = capi.prc_batch_create(capi.PRC_F32, capi.PRC_BC_CAVITY)
+    try:
+        assert capi.prc_batch_count(b) == (0, 0)
+        p = base()
+        fake_a, fake_b, fake_u = 256 * 1000, 256 * 3000, 256 * 5000  # never dereferenced
+        with pytest.raises(capi.PrcError):           # storage differs from the batch's
+            q = p.copy()
+            q.storage = capi.PRC_F64
+            capi.prc_batch_add(b, q, fake_a, fake_b, fake_u)
+        with pytest.raises(capi.PrcError):           # boundary type differs
+            q = p.copy()
+            q.bc = capi.PRC_BC_PERIODIC
+            capi.prc_batch_add(b, q, fake_a, fake_b, fake_u)
+        with pytest.raises(capi.PrcError):           # misaligned buffer
+            capi.prc_batch_add(b, p, fake_a + 4, fake_b, fake_u)
+        with pytest.raises(capi.PrcError):           # same buffer twice
+            capi.prc_batch_add(b, p, fake_a, fake_a, fake_u)
+        with pytest.raises(capi.PrcError):           # invalid problem
+            q = p.copy()
+            q.gamma = 0.0
+            capi.prc_batch_add(b, q, fake_a, fake_b, fake_u)
+        assert capi.prc_batch_count(b) == (0, 0)
+        assert capi.prc_batch_add(b, p, fake_a, fake_b, fake_u) == 0
+        assert capi.prc_batch_add(b, p, fake_b, fake_a, fake_u) == 1
+        assert capi.prc_batch_count(b) == (2, 2)
+        capi.prc_batch_remove(b, 0)
+        assert capi.prc_batch_count(b) == (2, 1)
+        for bad in (0, 2, -1):                        # removed, unknown, negative
+            with pytest.raises(capi.PrcError):
+                capi.prc_batch_remove(b, bad)
+        with pytest.raises(capi.PrcError):
+            capi.prc_batch_step(b, 3)                 # odd step counts are refused
+        with pytest.raises(capi.PrcError):
+            capi.prc_batch_solve(b, 1e-6, 100, 250)   # max_steps not a multiple
+        with pytest.raises(capi.PrcError):
+            capi.prc_batch_solve(b, 1e-6, 101, 202)   # odd check interval
+        for t in (-1, 3):
+            with pytest.raises(capi.PrcError):
+                capi.prc_batch_set_tile(b, t)
+        capi.prc_batch_set_tile(b, 2)
+    finally:
+        capi.prc_batch_destroy(b)
+
+
+@pytest.mark.parametrize("storage,bc", [(4, 0), (-1, 0), (1, 3)])
+def test_batch_create_rejects(storage, bc):
+    with pytest.raises(capi.PrcError):
+        capi.prc_batch_create(storage, bc)
