@@ -174,7 +174,8 @@ prc_status prc_solve(const prc_params *p, void *f_a, void *f_b, double *u_prev,
                      int64_t hist_cap, int64_t *hist_len, hipStream_t stream);
 
 /* Autotuner: time every tile shape of the sweep kernel (threads along x by
- * along y: 0 = 64 x 4, 1 = 64 x 8, 2 = 128 x 4) for this problem's storage,
+ * along y: 0 = 64 x 4, 1 = 64 x 8, 2 = 128 x 4, 3 = 32 x 8, 4 = 32 x 16) for
+ * this problem's storage,
  * boundaries and grid size, on two scratch state buffers that the call
  * allocates and frees itself (hipMalloc/hipFree), and use the fastest for
  * every later sweep of a problem with the same storage, boundaries and grid
@@ -279,7 +280,8 @@ prc_status prc_batch_solve(prc_batch *b, double tol, int64_t check_every, int64_
  * (may be NULL) receives it.  Synchronises the stream. */
 prc_status prc_batch_tune(prc_batch *b, int32_t *tile_out, hipStream_t stream);
 
-/* Use tile shape `tile` (0, 1, 2) for this batch's sweeps.  Host only. */
+/* Use tile shape `tile` (0 .. 4, as for prc_tune) for this batch's sweeps.
+ * Host only. */
 prc_status prc_batch_set_tile(prc_batch *b, int32_t tile);
 
 /* Message of the last failed call on this thread ("" if none). */

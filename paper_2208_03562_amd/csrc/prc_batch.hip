@@ -238,6 +238,8 @@ static prc_status launch_batch_sweep(const prc_batch &b, int parity, hipStream_t
     switch (batch_tile(b)) {
     case 1: return launch_batch_variants<ST, BC, 64, 8>(b, parity, s);
     case 2: return launch_batch_variants<ST, BC, 128, 4>(b, parity, s);
+    case 3: return launch_batch_variants<ST, BC, 32, 8>(b, parity, s);
+    case 4: return launch_batch_variants<ST, BC, 32, 16>(b, parity, s);
     default: return launch_batch_variants<ST, BC, 64, 4>(b, parity, s);
     }
 }

@@ -163,7 +163,9 @@ inline int red_blocks(const prc_params &p)
 struct TileShape {
     int tx, ty;
 };
-constexpr TileShape kTiles[] = {{64, 4}, {64, 8}, {128, 4}};
+// Narrow shapes waste fewer threads on grids whose width is not a multiple
+// of 64 (batches of small problems); a wavefront then spans two or four rows.
+constexpr TileShape kTiles[] = {{64, 4}, {64, 8}, {128, 4}, {32, 8}, {32, 16}};
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
 // run F<ST, BC>(args...) for the storage and boundary type of p

@@ -117,6 +117,8 @@ static prc_status launch_sweep_tile(const prc_params &p, int tile, const void *s
     switch (tile) {
     case 1: return launch_sweep_variant<ST, BC, 64, 8>(p, src, dst, s);
     case 2: return launch_sweep_variant<ST, BC, 128, 4>(p, src, dst, s);
+    case 3: return launch_sweep_variant<ST, BC, 32, 8>(p, src, dst, s);
+    case 4: return launch_sweep_variant<ST, BC, 32, 16>(p, src, dst, s);
     default: return launch_sweep_variant<ST, BC, 64, 4>(p, src, dst, s);
     }
 }

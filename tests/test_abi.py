@@ -155,7 +155,7 @@ def test_batch_host_checks():
             capi.prc_batch_solve(b, 1e-6, 100, 250)   # max_steps not a multiple
         with pytest.raises(capi.PrcError):
             capi.prc_batch_solve(b, 1e-6, 101, 202)   # odd check interval
-        for t in (-1, 3):
+        for t in (-1, 5):
             with pytest.raises(capi.PrcError):
                 capi.prc_batch_set_tile(b, t)
         capi.prc_batch_set_tile(b, 2)

@@ -155,7 +155,7 @@ def test_batch_tune_keeps_results(torch_cuda):
         c.add(lib_params(s))
     a.step(20)
     t = a.tune()          # sweeps f_a into f_b only: the state is unchanged
-    assert t in (0, 1, 2)
+    assert t in range(5)
     a.step(40)
     c.step(60)
     for i in range(5):

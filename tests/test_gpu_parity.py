@@ -259,7 +259,7 @@ def test_tile_shapes_give_identical_results(O, torch_cuda, storage):
     s = spec(300, 70, 2.0, 0.3, omega_nu=1.3, u_lid=0.05, storage=storage)
     noise = workloads.deviation_noise(300, 70, seed=11, amplitude=1e-3)
     outs = []
-    for tile in range(3):
+    for tile in range(5):
         sol = make_solver(s)
         capi.prc_set_tile(sol.p, tile)
         sol.set_state(noise)
@@ -276,7 +276,7 @@ def test_tune_returns_a_shape_and_results_are_unchanged(torch_cuda):
     a = make_solver(s)
     a.step(6)
     t = capi.prc_tune(a.p)
-    assert t in (0, 1, 2)
+    assert t in range(5)
     b = make_solver(s)
     b.step(6)
     capi.prc_set_tile(a.p, -1)
