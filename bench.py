@@ -106,6 +106,117 @@ def run_gpu(w: workloads.Cavity, steps: int, warmup: int):
     return res
 
 
+BATCH_TOL, BATCH_CHECK, BATCH_MAX_STEPS = 1e-7, 500, 100000
+SERVE_TOL, SERVE_CHECK, SERVE_MAX_STEPS = 1e-7, 500, 20000
+
+
+def run_batch(n_inst: int, solo_sample: int):
+    """Batched solve of the uneven-instance workload (seed 0): every instance
+    to R < 1e-7 with checks every 500 steps, at most 100000 steps; converged,
+    diverged and step-limited instances leave the batch at the check where
+    that happens.  Then the first `solo_sample` converged instances solved
+    one at a time (prc_solve) for comparison."""
+    import numpy as np
+    import torch
+    from paper_2208_03562_amd import capi, solver
+
+    insts = workloads.batch_instances(n_inst, seed=0)
+    stream = torch.cuda.Stream()
+    b = solver.Batch(stream=stream)
+    for it in insts:
+        b.add(solver.make_params(it.nx, it.ny, it.r, it.gamma, re=it.re, u_lid=it.u_lid))
+    tile = b.tune()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    status, steps, _ = b.solve(BATCH_TOL, BATCH_CHECK, BATCH_MAX_STEPS)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    nodes = np.array([it.nx * it.ny for it in insts], dtype=np.int64)
+    steps = np.array(steps, dtype=np.int64)
+    status = np.array(status)
+    upd = float((nodes * steps).sum())
+    conv = status == capi.PRC_MEMBER_CONVERGED
+    log(f"[bench] batch of {n_inst}: {wall:.2f} s, {upd / wall / 1e6:.0f} MLUPS, "
+        f"{int(conv.sum())} converged, tile {tile}")
+    b.close()
+    del b
+    # the same kind of solves one at a time
+    sel = [i for i in range(n_inst) if conv[i]][:solo_sample]
+    solo_t, solo_upd = 0.0, 0.0
+    for i in sel:
+        it = insts[i]
+        p = solver.make_params(it.nx, it.ny, it.r, it.gamma, re=it.re, u_lid=it.u_lid)
+        capi.prc_tune(p, stream.cuda_stream)
+        sol = solver.Solver(p, stream=stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st, n, _ = sol.solve(BATCH_TOL, BATCH_CHECK, BATCH_MAX_STEPS)
+        torch.cuda.synchronize()
+        solo_t += time.perf_counter() - t1
+        solo_upd += n * it.nx * it.ny
+        assert (st, n) == (int(status[i]), int(steps[i])), "solo and batched solves differ"
+        del sol
+    log(f"[bench] {len(sel)} of those one at a time: {solo_t:.2f} s, "
+        f"{solo_upd / max(solo_t, 1e-9) / 1e6:.0f} MLUPS")
+    names = {0: "converged", 1: "max_steps", -3: "diverged"}
+    return {
+        "workload": f"{n_inst} cavities, seed 0 (Nx, Ny log-uniform 64..512, r in 0.5/1/2/4, "
+                    f"gamma 0.05..1, Re 100..5000, U 0.05), FP32",
+        "tol": BATCH_TOL, "check_every": BATCH_CHECK, "max_steps": BATCH_MAX_STEPS,
+        "nodes": int(nodes.sum()), "node_updates": upd, "wall_s": round(wall, 3),
+        "mlups": round(upd / wall / 1e6, 1), "tile": tile,
+        "outcomes": {names[k]: int((status == k).sum()) for k in names},
+        "converged_steps_median": int(np.median(steps[conv])) if conv.any() else None,
+        "converged_per_s": round(float(conv.sum()) / wall, 3),
+        "one_at_a_time": {"instances": len(sel), "wall_s": round(solo_t, 3),
+                          "mlups": round(solo_upd / max(solo_t, 1e-9) / 1e6, 1),
+                          "note": "the first converged instances, each solved alone with "
+                                  "prc_solve (tuned tile); identical steps and status to the "
+                                  "batch"},
+        "speedup_vs_one_at_a_time": round((upd / wall) / (solo_upd / max(solo_t, 1e-9)), 2)
+        if sel else None,
+    }
+
+
+def run_serve(n_req: int, solo_req: int, mlups_hint: float):
+    """Serving: the seeded Poisson trace (seed 1, unit rate, scaled) of
+    steady-state solve requests, each to R < 1e-7 or 20000 steps.  The rate
+    is 80 % of the capacity implied by mlups_hint for requests that use their
+    whole step budget.  Then the first solo_req requests of the same trace
+    served one at a time."""
+    import numpy as np
+    from paper_2208_03562_amd import serving, solver
+
+    trace = workloads.poisson_trace(n_req, 1.0, seed=1)
+    ps = [solver.make_params(r.inst.nx, r.inst.ny, r.inst.r, r.inst.gamma, re=r.inst.re,
+                             u_lid=r.inst.u_lid) for r in trace]
+    mean_nodes = float(np.mean([p.nx * p.ny for p in ps]))
+    lam = 0.8 * mlups_hint * 1e6 / (mean_nodes * SERVE_MAX_STEPS)
+    arrivals = [r.arrival_s / lam for r in trace]
+    budget = 32 << 30
+    kw = dict(tol=SERVE_TOL, check_every=SERVE_CHECK, max_steps=SERVE_MAX_STEPS,
+              hbm_budget=budget)
+    on = serving.serve(ps, arrivals, **kw)
+    s_on = serving.summary(on)
+    log(f"[bench] serving {n_req} requests at {lam:.2f}/s: {s_on}")
+    one = serving.serve(ps[:solo_req], arrivals[:solo_req], max_active=1, **kw)
+    s_one = serving.summary(one)
+    s_on_head = serving.summary(on[:solo_req])
+    log(f"[bench] first {solo_req} one at a time: {s_one}")
+    same = all((a.status, a.steps) == (b.status, b.steps) for a, b in zip(on, one))
+    rnd = lambda d: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}  # noqa
+    return {
+        "workload": f"{n_req} requests, Poisson arrivals (seed 1) at {lam:.3f}/s; Nx log-uniform "
+                    "128..2048, Ny 128..1024, r, gamma, Re as the batch workload; FP32",
+        "tol": SERVE_TOL, "check_every": SERVE_CHECK, "max_steps": SERVE_MAX_STEPS,
+        "rate_per_s": round(lam, 4), "hbm_budget_bytes": budget,
+        "batched": rnd(s_on),
+        "batched_first": rnd(s_on_head),
+        "one_at_a_time_first": rnd(s_one),
+        "same_steps_and_status_alone": same,
+    }
+
+
 def run_cpu_baseline(w: workloads.Cavity, budget_s: float):
     import numpy as np  # noqa: F401
     from oracle import oracle as O
@@ -269,6 +380,10 @@ def main():
                     help="write profiles/traffic.json from the two counter runs in this folder")
     ap.add_argument("--trace-summary", default="",
                     help="print per-grid kernel durations of a kernel-trace run in this folder")
+    ap.add_argument("--batch-instances", type=int, default=256,
+                    help="instances of the batched-solve workload (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=200,
+                    help="requests of the serving trace (0: skip)")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=2000)
@@ -310,6 +425,10 @@ def main():
                 sweep_us=round(r["sweep_us"], 2), achieved_gbs=round(r["sweep_gbs"], 1),
                 frac=round(r["sweep_gbs"] / HBM_PEAK_GBS, 4),
                 bytes_per_node=BYTES_PER_NODE[wh.storage], diverged_at_step=r["diverged_at"])
+    batch = run_batch(args.batch_instances, 16) if args.batch_instances > 0 else None
+    serve = (run_serve(args.serve_requests, min(args.serve_requests, 50),
+                       batch["mlups"] if batch else main_res["mlups"])
+             if args.serve_requests > 0 else None)
     parity = oracle_parity(w, wc) if args.cpu_budget > 0 else None
     cpu = run_cpu_baseline(w, args.cpu_budget) if args.cpu_budget > 0 else None
     traffic = measured_traffic(w)
@@ -351,6 +470,8 @@ def main():
                              "residual_last": comp["residual_last"],
                              "diverged_at_step": comp["diverged_at"]},
         "hbm_grids": big or None,
+        "batched_solves": batch,
+        "serving": serve,
         "oracle_parity": parity,
         "cpu_baseline": cpu,
     }

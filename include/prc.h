@@ -284,6 +284,54 @@ prc_status prc_batch_tune(prc_batch *b, int32_t *tile_out, hipStream_t stream);
  * Host only. */
 prc_status prc_batch_set_tile(prc_batch *b, int32_t tile);
 
+/* ---- Serving: steady-state solve requests with continuous batching -----
+ *
+ * prc_serve runs a stream of steady-state solve requests (Sec. 5: each a
+ * problem driven to a converged state) that arrive over time.  Requests are
+ * admitted in arrival order while their device memory fits a budget; every
+ * admitted request joins one batch (prc_batch_*), which advances in
+ * intervals of check_every steps; after each interval's check, requests that
+ * converged, diverged or used up max_steps leave, their results are copied
+ * to the host and their memory goes back to the pool, and waiting requests
+ * join.  A request's arithmetic does not depend on the others: its result is
+ * bit for bit that of prc_solve on the same problem with the same tol,
+ * check_every and max_steps.
+ */
+typedef struct {
+    double arrival_s;  /* seconds after the start of prc_serve; non-decreasing */
+    prc_params p;      /* the problem; storage and bc must be the server's */
+    double *ux, *uy;   /* host double[ny][nx] each for the final velocity, or NULL */
+} prc_request;
+
+typedef struct {
+    int32_t status;    /* prc_member_status; PRC_EINVAL if the request was
+                          rejected (invalid problem, or larger than the budget) */
+    int32_t reserved;
+    int64_t steps;     /* time steps taken */
+    double residual;   /* relative residual of its last check */
+    double admit_s;    /* when its state was set up on the GPU (seconds) */
+    double done_s;     /* when its result was on the host (seconds) */
+} prc_result;
+
+typedef struct {
+    int32_t storage, bc;  /* of every request */
+    double tol;           /* convergence tolerance on the relative residual */
+    int64_t check_every;  /* even, > 0 */
+    int64_t max_steps;    /* multiple of check_every */
+    size_t hbm_budget;    /* device bytes for the requests' buffers: two states
+                             and a velocity snapshot (16 B/node) each */
+    int32_t max_active;   /* at most this many requests in the batch; 0 = no
+                             limit, 1 = one at a time */
+    int32_t tile;         /* sweep tile shape (0 .. 4), -1 for the default */
+} prc_serve_config;
+
+/* Serve requests reqs[0 .. n) (host array, arrivals non-decreasing) and write
+ * res[0 .. n) (host).  Allocates one pool of cfg->hbm_budget bytes
+ * (hipMalloc) for the requests' buffers and frees it before returning.
+ * Blocks until every request has its result; synchronises the stream. */
+prc_status prc_serve(const prc_serve_config *cfg, const prc_request *reqs, int32_t n,
+                     prc_result *res, hipStream_t stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *prc_last_error(void);
 

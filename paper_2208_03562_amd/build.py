@@ -8,9 +8,10 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libprc.so")
-SOURCES = [os.path.join(CSRC, "prc_lib.hip"), os.path.join(CSRC, "prc_batch.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("prc_lib.hip", "prc_batch.hip", "prc_serve.hip")]
 HEADERS = [os.path.join(CSRC, h) for h in ("prc_coef.hpp", "prc_device.hpp", "prc_collide.hpp",
-                                         "prc_sweep.hpp", "prc_host.hpp", "prc_reduce.hpp")] + [
+                                         "prc_sweep.hpp", "prc_host.hpp", "prc_reduce.hpp",
+                                         "prc_batch.hpp")] + [
     os.path.join(ROOT, "include", "prc.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

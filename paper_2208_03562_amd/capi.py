@@ -53,6 +53,24 @@ class prc_params(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class prc_request(ctypes.Structure):
+    _fields_ = [("arrival_s", ctypes.c_double), ("p", prc_params),
+                ("ux", ctypes.c_void_p), ("uy", ctypes.c_void_p)]
+
+
+class prc_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("steps", ctypes.c_int64), ("residual", ctypes.c_double),
+                ("admit_s", ctypes.c_double), ("done_s", ctypes.c_double)]
+
+
+class prc_serve_config(ctypes.Structure):
+    _fields_ = [("storage", ctypes.c_int32), ("bc", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("check_every", ctypes.c_int64), ("max_steps", ctypes.c_int64),
+                ("hbm_budget", ctypes.c_size_t), ("max_active", ctypes.c_int32),
+                ("tile", ctypes.c_int32)]
+
+
 class PrcError(RuntimeError):
     def __init__(self, fn: str, status: int, msg: str):
         super().__init__(f"{fn} -> {STATUS_NAMES.get(status, status)}: {msg}")
@@ -96,6 +114,8 @@ _PROTOS = {
                                        _VP]),
     "prc_batch_tune": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int32), _VP]),
     "prc_batch_set_tile": (ctypes.c_int, [_VP, ctypes.c_int32]),
+    "prc_serve": (ctypes.c_int, [ctypes.POINTER(prc_serve_config), ctypes.POINTER(prc_request),
+                                 ctypes.c_int32, ctypes.POINTER(prc_result), _VP]),
 }
 
 _lib = None
@@ -289,3 +309,14 @@ def prc_batch_tune(b: int, stream: int = 0) -> int:
 
 def prc_batch_set_tile(b: int, tile: int) -> None:
     _check("prc_batch_set_tile", lib().prc_batch_set_tile(b, int(tile)))
+
+
+# ---- serving -----------------------------------------------------------------
+
+def prc_serve(cfg: prc_serve_config, reqs, stream: int = 0):
+    """Serve a list of prc_request; returns the list of prc_result."""
+    n = len(reqs)
+    arr = (prc_request * max(1, n))(*reqs)
+    res = (prc_result * max(1, n))()
+    _check("prc_serve", lib().prc_serve(ctypes.byref(cfg), arr, n, res, stream))
+    return [res[i] for i in range(n)]

@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "prc.h"
+#include "prc_batch.hpp"
 #include "prc_coef.hpp"
 #include "prc_device.hpp"
 #include "prc_host.hpp"
@@ -93,7 +94,8 @@ struct Member {
     double *up;
     int32_t status;  // prc_member_status
     bool fresh;      // no velocity snapshot taken yet
-    int64_t steps;
+    int64_t steps;   // since the member joined
+    double R;        // relative residual of its last check
 };
 
 }  // namespace prc
@@ -119,6 +121,7 @@ struct prc_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     int gsteps = 0;
+    int calls_since_rebuild = 0;  // step calls served by the current tables
 };
 
 namespace prc {
@@ -196,6 +199,7 @@ static prc_status build_tables(prc_batch &b, hipStream_t s)
     }
     HIP_TRY(hipStreamSynchronize(s));
     b.dirty = false;
+    b.calls_since_rebuild = 0;
     return PRC_OK;
 }
 
@@ -292,7 +296,10 @@ static prc_status batch_steps(prc_batch &b, int64_t nsteps, hipStream_t s)
     const int gsteps = graph_steps();
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     HIP_TRY(hipStreamIsCapturing(s, &cap));
-    if (gsteps > 0 && cap == hipStreamCaptureStatusNone && nsteps >= 2 * gsteps) {
+    // graphs only for tables that have already served a call: a batch whose
+    // membership changes at every interval would otherwise capture each time
+    const bool stable = b.calls_since_rebuild++ > 0;
+    if (gsteps > 0 && stable && cap == hipStreamCaptureStatusNone && nsteps >= 2 * gsteps) {
         if (!b.gexec || b.gsteps != gsteps)
             if ((st = capture_graph(b, gsteps)) != PRC_OK) return st;
         for (; k + gsteps <= nsteps; k += gsteps) HIP_TRY(hipGraphLaunch(b.gexec, s));
@@ -392,6 +399,50 @@ static prc_status batch_ok(const prc_batch *b)
     return PRC_OK;
 }
 
+static void leave(prc_batch &b, int32_t id, int32_t status, std::vector<BatchLeft> *left)
+{
+    retire(b, id, status);
+    if (left) left->push_back({id, status, b.mem[id].steps, b.mem[id].R});
+}
+
+prc_status batch_interval(prc_batch *b, double tol, int64_t check_every, int64_t max_steps,
+                          std::vector<BatchChecked> *checked, std::vector<BatchLeft> *left,
+                          hipStream_t s)
+{
+    prc_status st = ensure_tables(*b, s);
+    if (st != PRC_OK) return st;
+    // velocity snapshots of members that have none yet (as prc_solve's first
+    // prc_residual)
+    std::vector<int32_t> slots;
+    for (size_t k = 0; k < b->active.size(); ++k)
+        if (b->mem[b->active[k]].fresh) slots.push_back((int32_t)k);
+    if (!slots.empty()) {
+        if ((st = batch_check(*b, &slots, s)) != PRC_OK) return st;
+        for (int32_t k : slots) b->mem[b->active[k]].fresh = false;
+    }
+    for (int32_t id : std::vector<int32_t>(b->active))
+        if (b->mem[id].steps >= max_steps) leave(*b, id, PRC_MEMBER_MAX_STEPS, left);
+    if (b->active.empty()) return PRC_OK;
+    if ((st = batch_steps(*b, check_every, s)) != PRC_OK) return st;
+    if ((st = batch_check(*b, nullptr, s)) != PRC_OK) return st;
+    const std::vector<int32_t> ids = b->active;
+    for (size_t k = 0; k < ids.size(); ++k) {
+        Member &m = b->mem[ids[k]];
+        m.steps += check_every;
+        const double *o = &b->h_out[4 * k];
+        // as prc_solve: a NaN in either sum makes R non-finite
+        m.R = o[1] > 0.0 ? std::sqrt(o[0] / o[1]) : (o[1] == 0.0 && o[0] == 0.0 ? 0.0 : INFINITY);
+        if (checked) checked->push_back({ids[k], m.R});
+        if (!std::isfinite(m.R) || !std::isfinite(o[2]) || !(o[3] < 1.0))
+            leave(*b, ids[k], PRC_MEMBER_DIVERGED, left);
+        else if (m.R < tol)
+            leave(*b, ids[k], PRC_MEMBER_CONVERGED, left);
+        else if (m.steps >= max_steps)
+            leave(*b, ids[k], PRC_MEMBER_MAX_STEPS, left);
+    }
+    return PRC_OK;
+}
+
 }  // namespace prc
 
 // ----------------------------------------------------------------- ABI --
@@ -439,7 +490,7 @@ prc_status prc_batch_add(prc_batch *b, const prc_params *p, void *f_a, void *f_b
     if (f_a == f_b) return fail(PRC_EINVAL, "f_a and f_b must be distinct buffers");
     if (!u_prev) return fail(PRC_EINVAL, "u_prev is NULL");
     if (b->mem.size() >= (size_t)INT32_MAX) return fail(PRC_EINVAL, "too many members");
-    b->mem.push_back(Member{*p, f_a, f_b, u_prev, PRC_MEMBER_ACTIVE, true, 0});
+    b->mem.push_back(Member{*p, f_a, f_b, u_prev, PRC_MEMBER_ACTIVE, true, 0, NAN});
     const int32_t id = (int32_t)(b->mem.size() - 1);
     b->active.push_back(id);
     b->dirty = true;
@@ -503,41 +554,16 @@ prc_status prc_batch_solve(prc_batch *b, double tol, int64_t check_every, int64_
     if (hist && hist_cap < 0) return fail(PRC_EINVAL, "hist_cap < 0");
     const size_t n_added = b->mem.size();
     std::vector<int64_t> nh(n_added, 0);
-    // velocity snapshots of members that have none yet
-    {
-        if ((st = ensure_tables(*b, stream)) != PRC_OK) return st;
-        std::vector<int32_t> slots;
-        for (size_t k = 0; k < b->active.size(); ++k)
-            if (b->mem[b->active[k]].fresh) slots.push_back((int32_t)k);
-        if (!slots.empty()) {
-            if ((st = batch_check(*b, &slots, stream)) != PRC_OK) return st;
-            for (int32_t k : slots) b->mem[b->active[k]].fresh = false;
+    std::vector<BatchChecked> checked;
+    do {
+        checked.clear();
+        if ((st = batch_interval(b, tol, check_every, max_steps, &checked, nullptr, stream)) != PRC_OK)
+            return st;
+        for (const BatchChecked &c : checked) {
+            if (hist && nh[c.id] < hist_cap) hist[(size_t)c.id * hist_cap + nh[c.id]] = c.R;
+            ++nh[c.id];
         }
-    }
-    // members that have already used up their steps leave at once
-    for (int32_t id : std::vector<int32_t>(b->active))
-        if (b->mem[id].steps >= max_steps) retire(*b, id, PRC_MEMBER_MAX_STEPS);
-    while (!b->active.empty()) {
-        if ((st = batch_steps(*b, check_every, stream)) != PRC_OK) return st;
-        if ((st = batch_check(*b, nullptr, stream)) != PRC_OK) return st;
-        const std::vector<int32_t> ids = b->active;
-        for (size_t k = 0; k < ids.size(); ++k) {
-            Member &m = b->mem[ids[k]];
-            m.steps += check_every;
-            const double *o = &b->h_out[4 * k];
-            // as prc_solve: a NaN in either sum makes R non-finite
-            const double R = o[1] > 0.0 ? std::sqrt(o[0] / o[1])
-                                        : (o[1] == 0.0 && o[0] == 0.0 ? 0.0 : INFINITY);
-            if (hist && nh[ids[k]] < hist_cap) hist[(size_t)ids[k] * hist_cap + nh[ids[k]]] = R;
-            ++nh[ids[k]];
-            if (!std::isfinite(R) || !std::isfinite(o[2]) || !(o[3] < 1.0))
-                retire(*b, ids[k], PRC_MEMBER_DIVERGED);
-            else if (R < tol)
-                retire(*b, ids[k], PRC_MEMBER_CONVERGED);
-            else if (m.steps >= max_steps)
-                retire(*b, ids[k], PRC_MEMBER_MAX_STEPS);
-        }
-    }
+    } while (!b->active.empty());
     for (size_t id = 0; id < n_added; ++id) {
         if (status) status[id] = b->mem[id].status;
         if (steps) steps[id] = b->mem[id].steps;

@@ -1,0 +1,84 @@
+"""Host side of ``prc_serve``: building request arrays and reading results.
+
+Argument marshalling and bookkeeping only; the serving loop (admission,
+batching, memory pool) runs in the library (``prc_serve``)."""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import capi
+from .capi import prc_params
+
+
+@dataclass
+class Served:
+    status: int
+    steps: int
+    residual: float
+    arrival_s: float
+    admit_s: float
+    done_s: float
+    ux: np.ndarray | None = None
+    uy: np.ndarray | None = None
+
+    @property
+    def latency_s(self) -> float:
+        return self.done_s - self.arrival_s
+
+
+def serve(problems: list[prc_params], arrivals: list[float], *, storage=capi.PRC_F32,
+          bc=capi.PRC_BC_CAVITY, tol=1e-7, check_every=500, max_steps=20000,
+          hbm_budget=8 << 30, max_active=0, tile=-1, fields=False, stream: int = 0):
+    """Run prc_serve on problems arriving at `arrivals` (seconds, sorted);
+    returns one :class:`Served` per request, with the final velocity fields
+    when ``fields`` is set."""
+    assert len(problems) == len(arrivals)
+    outs = []
+    reqs = []
+    for p, t in zip(problems, arrivals):
+        if fields:
+            ux = np.empty((p.ny, p.nx), dtype=np.float64)
+            uy = np.empty((p.ny, p.nx), dtype=np.float64)
+            outs.append((ux, uy))
+            reqs.append(capi.prc_request(float(t), p, ux.ctypes.data_as(ctypes.c_void_p),
+                                         uy.ctypes.data_as(ctypes.c_void_p)))
+        else:
+            outs.append((None, None))
+            reqs.append(capi.prc_request(float(t), p, None, None))
+    cfg = capi.prc_serve_config(storage=storage, bc=bc, tol=tol, check_every=check_every,
+                                max_steps=max_steps, hbm_budget=int(hbm_budget),
+                                max_active=max_active, tile=tile)
+    res = capi.prc_serve(cfg, reqs, stream)
+    return [Served(r.status, r.steps, r.residual, float(t), r.admit_s, r.done_s, ux, uy)
+            for r, t, (ux, uy) in zip(res, arrivals, outs)]
+
+
+def footprint_bytes(p: prc_params) -> int:
+    """Device bytes prc_serve sets aside for a request: two states and the
+    velocity snapshot, each rounded up to 256 bytes."""
+    rnd = lambda n: (n + 255) // 256 * 256  # noqa: E731
+    return 2 * rnd(capi.prc_state_bytes(p)) + rnd(16 * p.nx * p.ny)
+
+
+def summary(served: list[Served]) -> dict:
+    """Throughput and latency percentiles over the requests that ran."""
+    ran = [s for s in served if s.status != capi.PRC_EINVAL]
+    lat = np.array([s.latency_s for s in ran])
+    span = max(s.done_s for s in ran) - min(s.arrival_s for s in ran)
+    by = {}
+    for s in served:
+        by[s.status] = by.get(s.status, 0) + 1
+    names = {0: "converged", 1: "max_steps", -3: "diverged", -1: "rejected"}
+    return {
+        "requests": len(served),
+        "outcomes": {names.get(k, str(k)): v for k, v in sorted(by.items())},
+        "solves_per_s": len(ran) / span if span > 0 else None,
+        "converged_per_s": by.get(0, 0) / span if span > 0 else None,
+        "latency_p50_s": float(np.percentile(lat, 50)),
+        "latency_p99_s": float(np.percentile(lat, 99)),
+        "latency_max_s": float(lat.max()),
+        "span_s": span,
+    }

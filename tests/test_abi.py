@@ -167,3 +167,33 @@ def test_batch_host_checks():
 def test_batch_create_rejects(storage, bc):
     with pytest.raises(capi.PrcError):
         capi.prc_batch_create(storage, bc)
+
+
+def serve_cfg(**kw):
+    c = capi.prc_serve_config(storage=capi.PRC_F32, bc=capi.PRC_BC_CAVITY, tol=1e-6,
+                              check_every=100, max_steps=1000, hbm_budget=1 << 24,
+                              max_active=0, tile=-1)
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+@pytest.mark.parametrize("kw", [dict(check_every=99), dict(check_every=0), dict(max_steps=150),
+                                dict(tol=-1.0), dict(tile=5), dict(hbm_budget=100),
+                                dict(storage=7), dict(bc=4)])
+def test_serve_rejects_bad_config(kw):
+    with pytest.raises(capi.PrcError) as e:
+        capi.prc_serve(serve_cfg(**kw), [])
+    assert e.value.status == capi.PRC_EINVAL
+
+
+def test_serve_rejects_unordered_arrivals():
+    p = base()
+    reqs = [capi.prc_request(1.0, p, None, None), capi.prc_request(0.5, p, None, None)]
+    with pytest.raises(capi.PrcError) as e:
+        capi.prc_serve(serve_cfg(), reqs)
+    assert "non-decreasing" in str(e.value)
+
+
+def test_serve_empty_trace_is_a_no_op():
+    assert capi.prc_serve(serve_cfg(), []) == []

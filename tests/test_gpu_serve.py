@@ -1,0 +1,84 @@
+"""prc_serve: requests arriving over time, admitted by device-memory
+footprint, batched continuously.  Every request's result must be bit for bit
+that of prc_solve on the same problem -- whatever else is in the batch, and
+whether the server runs one request at a time or many."""
+import numpy as np
+import pytest
+
+from tests.common import lib_params, spec
+
+pytestmark = pytest.mark.gpu
+
+TOL, K, MAX = 1e-4, 100, 1200
+
+PROBLEMS = [
+    spec(64, 32, 2.0, 1.0, re=100.0, omega_nu=None, u_lid=0.05),
+    spec(37, 53, 1.0, 0.3, re=200.0, omega_nu=None, u_lid=0.03),
+    spec(130, 20, 0.5, 0.5, re=150.0, omega_nu=None, u_lid=0.02),
+    spec(48, 24, 2.0, 0.05, re=1000.0, omega_nu=None, u_lid=0.05),   # diverges
+    spec(70, 9, 4.0, 0.2, re=80.0, omega_nu=None, u_lid=0.04),
+    spec(40, 40, 1.0, 0.6, omega_nu=1.3, u_lid=0.02, fx=1e-6),
+    spec(200, 130, 1.0, 0.8, re=300.0, omega_nu=None, u_lid=0.05),
+    spec(90, 60, 2.0, 0.4, re=250.0, omega_nu=None, u_lid=0.03),
+]
+ARRIVALS = [0.0, 0.0, 0.01, 0.02, 0.02, 0.05, 0.08, 0.12]
+
+
+@pytest.fixture(scope="module")
+def alone():
+    """Each problem solved on its own with prc_solve: status, steps, last
+    residual and final velocity."""
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2208_03562_amd import solver
+    out = []
+    for s in PROBLEMS:
+        sol = solver.Solver(lib_params(s))
+        st, n, hist = sol.solve(TOL, K, MAX)
+        _, ux, uy = sol.macros()
+        out.append((st, n, hist[-1], ux.cpu().numpy(), uy.cpu().numpy()))
+    return out
+
+
+def check_same(served, alone):
+    for i, (r, (st, n, R, ux, uy)) in enumerate(zip(served, alone)):
+        assert (r.status, r.steps) == (st, n), (i, r.status, r.steps, st, n)
+        assert r.residual == R or (np.isinf(R) and np.isinf(r.residual)), i
+        if st != -3:
+            assert np.array_equal(r.ux, ux) and np.array_equal(r.uy, uy), i
+        assert r.admit_s >= r.arrival_s and r.done_s >= r.admit_s, i
+
+
+@pytest.mark.parametrize("max_active", [0, 1, 3])
+def test_served_results_are_the_solo_solves(alone, max_active):
+    from paper_2208_03562_amd import serving
+    served = serving.serve([lib_params(s) for s in PROBLEMS], ARRIVALS, tol=TOL, check_every=K,
+                           max_steps=MAX, hbm_budget=64 << 20, max_active=max_active,
+                           fields=True)
+    check_same(served, alone)
+
+
+def test_admission_waits_for_memory(alone):
+    """A pool that holds only the two largest requests at once: the others
+    wait for memory and still get their own solve's results."""
+    from paper_2208_03562_amd import serving
+    ps = [lib_params(s) for s in PROBLEMS]
+    fp = sorted(serving.footprint_bytes(p) for p in ps)
+    budget = fp[-1] + fp[-2]
+    served = serving.serve(ps, [0.0] * len(ps), tol=TOL, check_every=K, max_steps=MAX,
+                           hbm_budget=budget, fields=True)
+    check_same(served, alone)
+    admits = sorted(r.admit_s for r in served)
+    assert admits[-1] > admits[0]          # someone had to wait
+
+
+def test_rejected_requests(alone):
+    from paper_2208_03562_amd import capi, serving
+    ps = [lib_params(PROBLEMS[0]), lib_params(dict(PROBLEMS[1], storage="f64")),
+          lib_params(PROBLEMS[2])]
+    budget = serving.footprint_bytes(ps[0]) + serving.footprint_bytes(ps[2])
+    big = lib_params(spec(512, 512, 1.0, 1.0, omega_nu=1.0))    # larger than the pool
+    served = serving.serve(ps + [big], [0.0, 0.0, 0.0, 0.0], tol=TOL, check_every=K,
+                           max_steps=MAX, hbm_budget=budget, fields=True)
+    assert served[1].status == capi.PRC_EINVAL and served[3].status == capi.PRC_EINVAL
+    check_same([served[0], served[2]], [alone[0], alone[2]])
