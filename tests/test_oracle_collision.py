@@ -48,9 +48,12 @@ def random_state(rng, r, amp=0.3):
 
 
 @pytest.mark.parametrize("r", RS)
-def test_gamma1_unit_rates_gives_product_equilibrium(O, r):
+@pytest.mark.parametrize("frame", [0, 1])
+def test_gamma1_unit_rates_gives_product_equilibrium(O, r, frame):
+    """Central (PRC) and raw (PRNR) frames alike: with every rate one the
+    collision lands on the equilibrium, the product form at gamma = 1."""
     rng = np.random.default_rng(int(r * 10))
-    p = O.params(4, 4, r, 1.0, 1.0, corrections=0)
+    p = O.params(4, 4, r, 1.0, 1.0, corrections=0, frame=frame)
     for _ in range(10):
         f = random_state(rng, r)
         ft, d = O.collide_node(p, f)
@@ -102,9 +105,10 @@ def _mirror_check(O, p, perm, gsign, rng, r):
 
 @pytest.mark.parametrize("r", RS)
 @pytest.mark.parametrize("gamma", [1.0, 0.4])
-def test_mirror_symmetry(O, r, gamma):
+@pytest.mark.parametrize("frame", [0, 1])
+def test_mirror_symmetry(O, r, gamma, frame):
     rng = np.random.default_rng(21)
-    p = O.params(4, 4, r, gamma, 1.4, omega_xi=1.2)
+    p = O.params(4, 4, r, gamma, 1.4, omega_xi=1.2, frame=frame)
     for _ in range(5):
         _mirror_check(O, p, MIRROR_X, (-1, 1), rng, r)
         _mirror_check(O, p, MIRROR_Y, (1, -1), rng, r)
@@ -175,3 +179,42 @@ def test_equilibrium_is_fixed_point_without_corrections(O, r, gamma):
     feq = O.equilibrium_node(p, 1.02, 0.03 * min(1, r), -0.02 * min(1, r))
     ft, _ = O.collide_node(p, feq)
     np.testing.assert_allclose(ft, feq, rtol=1e-13, atol=1e-16)
+
+
+@pytest.mark.parametrize("r", [0.5, 2.0])
+def test_where_raw_and_central_frames_differ(O, r):
+    """Relaxing raw (PRNR) or central (PRC) moments gives the same result at
+    gamma = 1 when every moment is fully relaxed (all rates one, no
+    corrections); it differs once the shear rate or the corrections leave the
+    second-order moments off their base equilibria (the higher raw moments
+    then inherit them only in the central frame), and under preconditioning
+    even with full relaxation: the central k22
+    equilibrium c2^2 rho (below eq. 14) maps to a raw k22 with
+    (4/gamma^2 - 6/gamma + 3) rho ux^2 uy^2, the raw one (eq. 12) keeps 1."""
+    rng = np.random.default_rng(5)
+    f = random_state(rng, r)
+
+    def both(gamma, omega_nu, corrections=0):
+        return [O.collide_node(O.params(4, 4, r, gamma, omega_nu, frame=fr,
+                                        corrections=corrections), f, 1e-3, -2e-3)[0]
+                for fr in (0, 1)]
+
+    a, b = both(1.0, 1.0)
+    np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-15)
+    a, b = both(1.0, 1.6)
+    assert np.abs(a - b).max() > 1e-6
+    # the corrections enter the higher raw moments only in the central frame
+    a, b = both(1.0, 1.0, corrections=7)
+    assert np.abs(a - b).max() > 1e-7
+    a, b = both(0.5, 1.0)
+    # the full-relaxation difference is exactly the fourth-order one
+    rho = f.sum()
+    ux = (f * EX).sum() / rho
+    uy = (f * EYB * r).sum() / rho
+    g = 0.5
+    dm22 = (4 / g ** 2 - 6 / g + 3 - 1) * rho * ux ** 2 * uy ** 2
+    # a change dm22 of the raw moment m22 alone changes f by P^-1 S^-1 of it
+    e = np.zeros(9)
+    e[8] = 1.0
+    basis = O.populations_from_square_raw(O.unscale_rect(r, e))
+    np.testing.assert_allclose(a - b, dm22 * basis, rtol=1e-9, atol=1e-16)
