@@ -82,10 +82,14 @@ struct DevBuf {
     }
 };
 
-// Sweep variants: the method itself (every correction, no force) and the rest.
+// Sweep variants: the method itself (every correction, no force, central
+// frame) and the rest, as for the single-problem sweep.
 inline int variant_of(const prc_params &p)
 {
-    return (p.corrections == PRC_CORR_ALL && p.fx == 0.0 && p.fy == 0.0) ? 0 : 1;
+    return (p.corrections == PRC_CORR_ALL && p.fx == 0.0 && p.fy == 0.0 &&
+            p.frame == PRC_FRAME_CENTRAL)
+               ? 0
+               : 1;
 }
 
 struct Member {

@@ -28,6 +28,7 @@ struct Coef {
     uint32_t plane_bytes;   // bytes from one population plane to the next
     uint32_t state_bytes;   // bytes of the whole state
     int32_t corr;           // correction bitmask (generic kernels only)
+    int32_t frame;          // prc_frame (generic kernels only)
     int32_t tiles_x, tiles_y, tiles_per_xcd;  // sweep tile grid (set per launch)
     CT r, r2;               // y lattice speed and its square (scaling S)
     CT hinv_r, hinv_r2;     // 1/(2r), 1/(2r^2) (S^-1 with the halves of P^-1)
@@ -47,6 +48,8 @@ struct Coef {
     CT qfx, qfy;            // Q_gamma F (central source moments, eq. 13-central)
     CT sxi2, snu2, snu;     // 2 (1 - omega_xi/2), 2 (1 - omega_nu/2), 1 - omega_nu/2
     CT lid;                 // rho0 U c2 / (2 r^2): wall momentum term of a diagonal link
+    CT ig, igg;             // 1/gamma, 1/gamma^2 (raw-moment equilibria, eq. 12)
+    CT rqfx, rqfy;          // F / gamma^2 (raw source moments, eq. 13)
     CT gxa, gxb, gya, gyb;  // density-gradient stencil weights
 };
 
@@ -72,6 +75,7 @@ inline Coef<CT> make_coef(const prc_params &p, int64_t row_stride, int64_t plane
     c.plane_bytes = (uint32_t)(plane_stride * elem);
     c.state_bytes = (uint32_t)(total * elem);
     c.corr = p.corrections;
+    c.frame = p.frame;
     c.r = CT(r);
     c.r2 = CT(r * r);
     c.hinv_r = CT(0.5 / r);
@@ -111,6 +115,10 @@ inline Coef<CT> make_coef(const prc_params &p, int64_t row_stride, int64_t plane
     c.snu2 = CT(2.0 - p.omega_nu);
     c.snu = CT(1.0 - 0.5 * p.omega_nu);
     c.lid = CT(p.rho0 * p.u_lid * c2 / (2.0 * r * r));
+    c.ig = CT(1.0 / g);
+    c.igg = CT(1.0 / (g * g));
+    c.rqfx = CT(p.fx / (g * g));
+    c.rqfy = CT(p.fy / (g * g));
     c.gxa = CT(0.5 * (1.0 - c2 / (r * r)));
     c.gxb = CT(0.25 * c2 / (r * r));
     c.gya = CT((1.0 - c2) / (2.0 * r));

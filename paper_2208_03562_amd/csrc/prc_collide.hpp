@@ -22,11 +22,61 @@
 //  * The correction terms of eq. 38-40 need rho times the strain rates of
 //    eq. 48; the coefficients of eq. 46 all carry a factor rho, so the solve
 //    is done for rho dxux, rho dyuy directly and rho never appears.
+//
+// collide_raw is the same update with the moments relaxed in the rest frame
+// (raw moments, the PRNR-LBM of Sec. 4.1 used for comparison in Sec. 6): raw
+// equilibria of eq. 12, raw sources of eq. 13, the same corrections.
 #pragma once
 
 #include "prc_device.hpp"
 
 namespace prc {
+
+// Correction terms of the second-order equilibria (eq. 38-40) with the local
+// strain rates of eq. 43-48, from the second-order non-equilibrium parts
+// n2s = k2s - k2s_eq and n2d = k2d - k2d_eq (the same in the central and the
+// raw frame).  The solve is done for rho dxux, rho dyuy: the coefficients of
+// eq. 46 all carry a factor rho, so rho never appears.
+template <typename CT, bool ALL>
+__device__ __forceinline__ void corrections(const Coef<CT> &c, CT ux, CT uy, CT ux2, CT uy2, CT uxy,
+                                            CT n2s, CT n2d, CT gx, CT gy, CT &cor2s, CT &cor2d,
+                                            CT &cor11)
+{
+    cor2s = CT(0);
+    cor2d = CT(0);
+    cor11 = CT(0);
+    const int corr = ALL ? PRC_CORR_ALL : c.corr;
+    if (!corr) return;
+    const CT pux = c.Pg * ux2, puy = c.Pg * uy2, qux = c.Qg * ux2, quy = c.Qg * uy2;
+    const CT bx = (pux + quy) + c.a1, by = (puy + qux) + c.a2;
+    const CT sx = (pux - quy) + c.a1, sy = (puy - qux) + c.a2;
+    const CT Agx = c.Ab * ux * gx, Bgy = c.Bb * uy * gy;  // -e_b = Agx + Bgy
+    CT Dx = CT(0), Dy = CT(0);                            // rho dxux, rho dyuy
+    if (corr & (PRC_CORR_THETA | PRC_CORR_K11)) {
+        const CT R2s = n2s - (Agx + Bgy);
+        const CT R2d = n2d + (Bgy - Agx);
+        const CT cbx = c.cb0 + CT(0.5) * bx, cby = c.cb0 + CT(0.5) * by;
+        const CT csx = CT(0.5) * sx - c.cs0, csy = c.cs0 - CT(0.5) * sy;
+        const CT det = cbx * csy - csx * cby;
+        // one reciprocal serves both divisions of eq. 48
+        const CT ip = recip(det * cby);
+        Dx = (csy * R2s - cby * R2d) * (cby * ip);
+        Dy = (R2s - cbx * Dx) * (det * ip);
+    }
+    if (corr & PRC_CORR_THETA) {
+        // theta_bx = -bx rho h_xi, theta_by = -by rho h_xi, theta_sx =
+        // -sx rho h_nu, theta_sy = -sy rho h_nu; k2d takes theta_sx dxux
+        // - theta_sy dyuy
+        cor2s = c.mhxi * (bx * Dx + by * Dy);
+        cor2d = c.mhnu * (sx * Dx - sy * Dy);
+    }
+    if (corr & PRC_CORR_LAMBDA) {
+        cor2s += c.mhxi2 * (Agx + Bgy);
+        cor2d += c.mhnu2 * (Agx - Bgy);
+    }
+    if (corr & PRC_CORR_K11)
+        cor11 = c.kq11 * uxy * (Dx + Dy) + c.kl11 * (uy * gx + ux * gy);
+}
 
 // FORCE: the body force may be nonzero.  ALL: every correction term is on
 // (the method); otherwise the correction bitmask is read at run time.
@@ -98,39 +148,9 @@ __device__ __forceinline__ void collide(const Coef<CT> &c, CT d[9], CT gx, CT gy
     const CT e11 = irh * uxy;
 
     // corrections (eq. 38-40) with the local strain rates (eq. 43-48)
-    CT cor2s = CT(0), cor2d = CT(0), cor11 = CT(0);
-    const int corr = ALL ? PRC_CORR_ALL : c.corr;
-    if (corr) {
-        const CT pux = c.Pg * ux2, puy = c.Pg * uy2, qux = c.Qg * ux2, quy = c.Qg * uy2;
-        const CT bx = (pux + quy) + c.a1, by = (puy + qux) + c.a2;
-        const CT sx = (pux - quy) + c.a1, sy = (puy - qux) + c.a2;
-        const CT Agx = c.Ab * ux * gx, Bgy = c.Bb * uy * gy;  // -e_b = Agx + Bgy
-        CT Dx = CT(0), Dy = CT(0);                            // rho dxux, rho dyuy
-        if (corr & (PRC_CORR_THETA | PRC_CORR_K11)) {
-            const CT R2s = (k2s - e2s) - (Agx + Bgy);
-            const CT R2d = (k2d - e2d) + (Bgy - Agx);
-            const CT cbx = c.cb0 + CT(0.5) * bx, cby = c.cb0 + CT(0.5) * by;
-            const CT csx = CT(0.5) * sx - c.cs0, csy = c.cs0 - CT(0.5) * sy;
-            const CT det = cbx * csy - csx * cby;
-            // one reciprocal serves both divisions of eq. 48
-            const CT ip = recip(det * cby);
-            Dx = (csy * R2s - cby * R2d) * (cby * ip);
-            Dy = (R2s - cbx * Dx) * (det * ip);
-        }
-        if (corr & PRC_CORR_THETA) {
-            // theta_bx = -bx rho h_xi, theta_by = -by rho h_xi, theta_sx =
-            // -sx rho h_nu, theta_sy = -sy rho h_nu; k2d takes theta_sx dxux
-            // - theta_sy dyuy
-            cor2s = c.mhxi * (bx * Dx + by * Dy);
-            cor2d = c.mhnu * (sx * Dx - sy * Dy);
-        }
-        if (corr & PRC_CORR_LAMBDA) {
-            cor2s += c.mhxi2 * (Agx + Bgy);
-            cor2d += c.mhnu2 * (Agx - Bgy);
-        }
-        if (corr & PRC_CORR_K11)
-            cor11 = c.kq11 * uxy * (Dx + Dy) + c.kl11 * (uy * gx + ux * gy);
-    }
+    CT cor2s, cor2d, cor11;
+    corrections<CT, ALL>(c, ux, uy, ux2, uy2, uxy, k2s - e2s, k2d - e2d, gx, gy, cor2s, cor2d,
+                         cor11);
 
     // moment increments of the relaxation (Appendix A), B^-1 folded in
     CT d2s = c.om_xi * ((e2s + cor2s) - k2s);
@@ -178,6 +198,104 @@ __device__ __forceinline__ void collide(const Coef<CT> &c, CT d[9], CT gx, CT gy
         const CT h1 = CT(0.5) * R1, h2 = CT(0.5) * R2;
         q[j][0] += h2 - h1;
         q[j][1] += K0 - R2;
+        q[j][2] += h2 + h1;
+    }
+#pragma unroll
+    for (int a = 0; a < 9; ++a) d[a] = q[QJ[a]][QI[a]];
+}
+
+// Raw-moment (rest-frame) collision, PRNR-LBM.  Deviations and incremental
+// form as in collide(); the raw moments of rho0 w are exactly the constant
+// tensor rho0 (1,0,c2)x(1,0,c2), so the raw moments of the deviations are
+// those of f minus that tensor, and so are the equilibria written below.
+template <typename CT, bool FORCE>
+__device__ __forceinline__ void collide_raw(const Coef<CT> &c, CT d[9], CT gx, CT gy)
+{
+    CT q[3][3];  // [e_y + 1][e_x + 1]
+#pragma unroll
+    for (int a = 0; a < 9; ++a) q[QJ[a]][QI[a]] = d[a];
+    CT X0[3], X1[3], X2[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        X1[j] = q[j][2] - q[j][0];
+        X2[j] = q[j][2] + q[j][0];
+        X0[j] = X2[j] + q[j][1];
+    }
+    const CT drho = (X0[0] + X0[1]) + X0[2];
+    const CT rho = c.rho0 + drho;
+    const CT irho = recip(rho);
+    CT jx = (X1[0] + X1[1]) + X1[2], jy = c.r * (X0[2] - X0[0]);
+    if (FORCE) {
+        jx += c.fxh;
+        jy += c.fyh;
+    }
+    const CT ux = jx * irho, uy = jy * irho;
+    const CT ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
+    const CT u2s = ux2 + uy2;
+
+    // raw y-moments (lattice speed r) of each raw x-moment
+    auto yraw = [&](CT A, CT B, CT Cc, CT &M1, CT &M2) {
+        M1 = c.r * (Cc - A);
+        M2 = c.r2 * (Cc + A);
+        (void)B;
+    };
+    CT M01, M02, M11, M12, M21, M22;
+    yraw(X0[0], X0[1], X0[2], M01, M02);
+    yraw(X1[0], X1[1], X1[2], M11, M12);
+    yraw(X2[0], X2[1], X2[2], M21, M22);
+    (void)M01;
+    const CT M20 = (X2[0] + X2[1]) + X2[2];
+    const CT m2s = M20 + M02, m2d = M20 - M02;
+
+    // raw equilibria (eq. 12) minus rho0 (1,0,c2)x(1,0,c2)
+    const CT igr = c.ig * rho;
+    const CT e2s = c.c2x2 * drho + igr * u2s;
+    const CT e2d = igr * (ux2 - uy2);
+    const CT e11 = igr * uxy;
+
+    CT cor2s, cor2d, cor11;
+    corrections<CT, false>(c, ux, uy, ux2, uy2, uxy, m2s - e2s, m2d - e2d, gx, gy, cor2s, cor2d,
+                           cor11);
+
+    CT d2s = c.om_xi * ((e2s + cor2s) - m2s);
+    CT d2d = c.om_nu * ((e2d + cor2d) - m2d);
+    CT d11 = c.om_nu * ((e11 + cor11) - M11);
+    if (FORCE) {
+        // raw source moments (eq. 13) with weights 1 - omega/2
+        d2s += c.sxi2 * (c.rqfx * ux + c.rqfy * uy);
+        d2d += c.snu2 * (c.rqfx * ux - c.rqfy * uy);
+        d11 += c.snu * (c.rqfx * uy + c.rqfy * ux);
+    }
+    const CT d21 = c.om_3 * (rho * (c.c2 * uy + c.igg * ux2 * uy) - M21);
+    const CT d12 = c.om_3 * (rho * (c.c2 * ux + c.igg * uy2 * ux) - M12);
+    const CT d22 = c.om_4 * ((c.c2sq * drho + rho * (c.c2 * u2s + ux2 * uy2)) - M22);
+    const CT d20 = CT(0.5) * (d2s + d2d);
+    const CT d02 = CT(0.5) * (d2s - d2d);
+
+    // f~ = f + P^-1 S^-1 dm: y-transform back for each x-moment (the first
+    // raw moments change by F/gamma, k00 not at all) ...
+    CT G[3][3];  // [x-moment][e_y + 1]
+    auto yinv = [&](CT K0, CT K1, CT K2, CT *g) {
+        const CT a = c.hinv_r * K1, b = c.hinv_r2 * K2;  // halves
+        g[0] = b - a;
+        g[1] = K0 - CT(2) * b;
+        g[2] = b + a;
+    };
+    if (FORCE) {
+        yinv(CT(0), c.fyg, d02, G[0]);
+        yinv(c.fxg, d11, d12, G[1]);
+    } else {
+        yinv(CT(0), CT(0), d02, G[0]);
+        yinv(CT(0), d11, d12, G[1]);
+    }
+    yinv(d20, d21, d22, G[2]);
+    // ... then the x-transform back for each row, added to the populations
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const CT K0 = G[0][j], K1 = G[1][j], K2 = G[2][j];
+        const CT h1 = CT(0.5) * K1, h2 = CT(0.5) * K2;
+        q[j][0] += h2 - h1;
+        q[j][1] += K0 - K2;
         q[j][2] += h2 + h1;
     }
 #pragma unroll

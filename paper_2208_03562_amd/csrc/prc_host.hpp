@@ -124,8 +124,8 @@ inline prc_status validate(const prc_params *p)
         return fail(PRC_EINVAL, "unknown storage %d", p->storage);
     if (p->corrections < 0 || p->corrections > PRC_CORR_ALL)
         return fail(PRC_EINVAL, "corrections bitmask out of range");
-    if (p->frame != PRC_FRAME_CENTRAL)
-        return fail(PRC_EINVAL, "frame %d is not available in this library", p->frame);
+    if (p->frame != PRC_FRAME_CENTRAL && p->frame != PRC_FRAME_RAW)
+        return fail(PRC_EINVAL, "unknown frame %d", p->frame);
     int64_t row, plane, total;
     layout(*p, row, plane, total);
     // byte offsets into one state buffer are 32-bit (buffer addressing)

@@ -91,7 +91,14 @@ __device__ __forceinline__ void tile_finish(const Coef<typename Mem<ST>::CT> &c,
     const CT gx = c.gxa * (rE - rW) + c.gxb * ((rNE - rNW) + (rSE - rSW));
     const CT gy = c.gya * (rN - rS) + c.gyb * ((rNE + rNW) - (rSE + rSW));
 
-    collide<CT, FORCE, ALL>(c, d, gx, gy);
+    if constexpr (ALL) {
+        collide<CT, FORCE, ALL>(c, d, gx, gy);
+    } else {
+        if (c.frame == PRC_FRAME_RAW)
+            collide_raw<CT, FORCE>(c, d, gx, gy);
+        else
+            collide<CT, FORCE, ALL>(c, d, gx, gy);
+    }
 
     const uint32_t o = (uint32_t)y * c.row_bytes + (uint32_t)x * E;
 #pragma unroll
