@@ -162,9 +162,14 @@ static prc_status build_tables(prc_batch &b, hipStream_t s)
     b.h_res.clear();
     b.h_fin.clear();
     int32_t part = 0;
+    // the members' buffers share the last-level cache: non-temporal stores
+    // when all of them together do not fit it
+    int64_t pair_bytes = 0;
+    for (size_t k = 0; k < n; ++k) pair_bytes += 2 * (int64_t)coef_of<ST>(b.mem[b.active[k]].p).state_bytes;
     for (size_t k = 0; k < n; ++k) {
         const Member &m = b.mem[b.active[k]];
         bm[k].c = coef_of<ST>(m.p);
+        bm[k].c.nt = pair_bytes > kNtPairBytes;
         bm[k].buf[0] = m.fa;
         bm[k].buf[1] = m.fb;
         bm[k].u_prev = m.up;

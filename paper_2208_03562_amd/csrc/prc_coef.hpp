@@ -19,6 +19,9 @@ namespace prc {
 
 // Number of XCDs the hardware distributes workgroups over round-robin.
 constexpr int kXcds = 8;
+// Two state buffers larger than this do not stay in the 256 MB last-level
+// cache from one sweep to the next: their stores are non-temporal.
+constexpr int64_t kNtPairBytes = (int64_t)160 << 20;
 
 template <typename CT>
 struct Coef {
@@ -29,6 +32,7 @@ struct Coef {
     uint32_t state_bytes;   // bytes of the whole state
     int32_t corr;           // correction bitmask (generic kernels only)
     int32_t frame;          // prc_frame (generic kernels only)
+    int32_t nt;             // store the new state non-temporally
     int32_t tiles_x, tiles_y, tiles_per_xcd;  // sweep tile grid (set per launch)
     CT r, r2;               // y lattice speed and its square (scaling S)
     CT hinv_r, hinv_r2;     // 1/(2r), 1/(2r^2) (S^-1 with the halves of P^-1)
@@ -76,6 +80,7 @@ inline Coef<CT> make_coef(const prc_params &p, int64_t row_stride, int64_t plane
     c.state_bytes = (uint32_t)(total * elem);
     c.corr = p.corrections;
     c.frame = p.frame;
+    c.nt = 2 * total * elem > kNtPairBytes;
     c.r = CT(r);
     c.r2 = CT(r * r);
     c.hinv_r = CT(0.5 / r);

@@ -35,6 +35,12 @@ constexpr int QJ[9] = {1, 1, 2, 1, 0, 2, 2, 0, 0};
 // three address registers (one per source row) plus immediate offsets.
 using rsrc_t = __amdgpu_buffer_rsrc_t;
 constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit data (gfx9 family)
+// Cache policy bits of buffer accesses: kNt marks a non-temporal (streaming)
+// access.  The sweeps store non-temporally when the two state buffers do not
+// fit the last-level cache (the new state is read by the next sweep only,
+// after every other line of this one has been written); a state that fits is
+// stored normally so that the next sweep finds it in the cache.
+constexpr int kNt = 2;
 
 __device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint32_t bytes)
 {
@@ -45,51 +51,59 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint32_t bytes)
 template <typename ST> struct Mem;
 template <> struct Mem<double> {
     using CT = double;
+    template <int POL = 0>
     static __device__ __forceinline__ double ld(rsrc_t r, uint32_t v, uint32_t s)
     {
-        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0));
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, POL));
     }
+    template <int POL = 0>
     static __device__ __forceinline__ void st(rsrc_t r, uint32_t v, uint32_t s, double x)
     {
         using v2u = __attribute__((ext_vector_type(2))) unsigned int;
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, x), r, v, s, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, x), r, v, s, POL);
     }
 };
 template <> struct Mem<float> {
     using CT = float;
+    template <int POL = 0>
     static __device__ __forceinline__ float ld(rsrc_t r, uint32_t v, uint32_t s)
     {
-        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, POL));
     }
+    template <int POL = 0>
     static __device__ __forceinline__ void st(rsrc_t r, uint32_t v, uint32_t s, float x)
     {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, x), r, v, s, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, x), r, v, s, POL);
     }
 };
 template <> struct Mem<__half> {
     using CT = float;
+    template <int POL = 0>
     static __device__ __forceinline__ float ld(rsrc_t r, uint32_t v, uint32_t s)
     {
         return __half2float(
-            __builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0)));
+            __builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, v, s, POL)));
     }
+    template <int POL = 0>
     static __device__ __forceinline__ void st(rsrc_t r, uint32_t v, uint32_t s, float x)
     {
         __builtin_amdgcn_raw_buffer_store_b16(
-            __builtin_bit_cast(unsigned short, __float2half_rn(x)), r, v, s, 0);
+            __builtin_bit_cast(unsigned short, __float2half_rn(x)), r, v, s, POL);
     }
 };
 template <> struct Mem<__hip_bfloat16> {
     using CT = float;
+    template <int POL = 0>
     static __device__ __forceinline__ float ld(rsrc_t r, uint32_t v, uint32_t s)
     {
         return __bfloat162float(__builtin_bit_cast(
-            __hip_bfloat16, __builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0)));
+            __hip_bfloat16, __builtin_amdgcn_raw_buffer_load_b16(r, v, s, POL)));
     }
+    template <int POL = 0>
     static __device__ __forceinline__ void st(rsrc_t r, uint32_t v, uint32_t s, float x)
     {
         __builtin_amdgcn_raw_buffer_store_b16(
-            __builtin_bit_cast(unsigned short, __float2bfloat16(x)), r, v, s, 0);
+            __builtin_bit_cast(unsigned short, __float2bfloat16(x)), r, v, s, POL);
     }
 };
 

@@ -101,8 +101,13 @@ __device__ __forceinline__ void tile_finish(const Coef<typename Mem<ST>::CT> &c,
     }
 
     const uint32_t o = (uint32_t)y * c.row_bytes + (uint32_t)x * E;
+    if (c.nt) {
 #pragma unroll
-    for (int a = 0; a < 9; ++a) Mem<ST>::st(rd, o, a * c.plane_bytes, d[a]);
+        for (int a = 0; a < 9; ++a) Mem<ST>::template st<kNt>(rd, o, a * c.plane_bytes, d[a]);
+    } else {
+#pragma unroll
+        for (int a = 0; a < 9; ++a) Mem<ST>::st(rd, o, a * c.plane_bytes, d[a]);
+    }
 }
 
 // XCD-aware tile order: the hardware hands workgroup i to XCD i mod 8.  Each
