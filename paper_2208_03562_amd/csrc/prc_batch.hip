@@ -82,15 +82,9 @@ struct DevBuf {
     }
 };
 
-// Sweep variants: the method itself (every correction, no force, central
-// frame) and the rest, as for the single-problem sweep.
-inline int variant_of(const prc_params &p)
-{
-    return (p.corrections == PRC_CORR_ALL && p.fx == 0.0 && p.fy == 0.0 &&
-            p.frame == PRC_FRAME_CENTRAL)
-               ? 0
-               : 1;
-}
+// Sweep variants, as for the single-problem sweep: the method as the paper
+// runs it, and everything else.
+inline int variant_of(const prc_params &p) { return is_plain_method(p) ? 0 : 1; }
 
 struct Member {
     prc_params p;

@@ -36,6 +36,7 @@ struct Coef {
     int32_t tiles_x, tiles_y, tiles_per_xcd;  // sweep tile grid (set per launch)
     CT r, r2;               // y lattice speed and its square (scaling S)
     CT hinv_r, hinv_r2;     // 1/(2r), 1/(2r^2) (S^-1 with the halves of P^-1)
+    CT qinv_r, qinv_r2;     // 1/(4r), 1/(4r^2) (with the halves of both axes)
     CT rho0, c2, c2x2, c2sq, c2rho0;  // c2 = c_s^2; 2 c2; c2^2; c2 rho0
     CT ig1;                 // 1/gamma - 1
     CT Pg, Qg;              // 4/gamma^2 - 1/gamma, 1/gamma^2 - 1/gamma
@@ -85,6 +86,8 @@ inline Coef<CT> make_coef(const prc_params &p, int64_t row_stride, int64_t plane
     c.r2 = CT(r * r);
     c.hinv_r = CT(0.5 / r);
     c.hinv_r2 = CT(0.5 / (r * r));
+    c.qinv_r = CT(0.25 / r);
+    c.qinv_r2 = CT(0.25 / (r * r));
     c.rho0 = CT(p.rho0);
     c.c2 = CT(c2);
     c.c2x2 = CT(2.0 * c2);

@@ -47,9 +47,10 @@ __device__ __forceinline__ void corrections(const Coef<CT> &c, CT ux, CT uy, CT 
     cor11 = CT(0);
     const int corr = ALL ? PRC_CORR_ALL : c.corr;
     if (!corr) return;
-    const CT pux = c.Pg * ux2, puy = c.Pg * uy2, qux = c.Qg * ux2, quy = c.Qg * uy2;
-    const CT bx = (pux + quy) + c.a1, by = (puy + qux) + c.a2;
-    const CT sx = (pux - quy) + c.a1, sy = (puy - qux) + c.a2;
+    // bx = P ux^2 + Q uy^2 + a1, sx = P ux^2 - Q uy^2 + a1 (likewise by, sy)
+    const CT tx = c.Pg * ux2 + c.a1, ty = c.Pg * uy2 + c.a2;
+    const CT bx = tx + c.Qg * uy2, sx = tx - c.Qg * uy2;
+    const CT by = ty + c.Qg * ux2, sy = ty - c.Qg * ux2;
     const CT Agx = c.Ab * ux * gx, Bgy = c.Bb * uy * gy;  // -e_b = Agx + Bgy
     CT Dx = CT(0), Dy = CT(0);                            // rho dxux, rho dyuy
     if (corr & (PRC_CORR_THETA | PRC_CORR_K11)) {
@@ -78,8 +79,10 @@ __device__ __forceinline__ void corrections(const Coef<CT> &c, CT ux, CT uy, CT 
         cor11 = c.kq11 * uxy * (Dx + Dy) + c.kl11 * (uy * gx + ux * gy);
 }
 
-// FORCE: the body force may be nonzero.  ALL: every correction term is on
-// (the method); otherwise the correction bitmask is read at run time.
+// FORCE: the body force may be nonzero.  ALL: the method as the paper runs
+// it -- every correction term on and unit rates for the non-hydrodynamic
+// moments (omega_xi = omega_1 = omega_3 = omega_4 = 1, Appendix A); otherwise
+// the correction bitmask and all rates are read at run time.
 template <typename CT, bool FORCE, bool ALL>
 __device__ __forceinline__ void collide(const Coef<CT> &c, CT d[9], CT gx, CT gy)
 {
@@ -153,7 +156,7 @@ __device__ __forceinline__ void collide(const Coef<CT> &c, CT d[9], CT gx, CT gy
                          cor11);
 
     // moment increments of the relaxation (Appendix A), B^-1 folded in
-    CT d2s = c.om_xi * ((e2s + cor2s) - k2s);
+    CT d2s = ALL ? (e2s + cor2s) - k2s : c.om_xi * ((e2s + cor2s) - k2s);
     CT d2d = c.om_nu * ((e2d + cor2d) - k2d);
     CT d11 = c.om_nu * ((e11 + cor11) - k11);
     if (FORCE) {
@@ -163,42 +166,56 @@ __device__ __forceinline__ void collide(const Coef<CT> &c, CT d[9], CT gx, CT gy
         d11 += c.snu * (c.qfx * uy + c.qfy * ux);
     }
     const CT g3r = c.g3 * rho;
-    const CT d21 = c.om_3 * (g3r * ux2 * uy - k21);
-    const CT d12 = c.om_3 * (g3r * ux * uy2 - k12);
-    const CT d22 = c.om_4 * (c.c2sq * drho - k22);
-    const CT d20 = CT(0.5) * (d2s + d2d);
+    const CT d21 = ALL ? g3r * ux2 * uy - k21 : c.om_3 * (g3r * ux2 * uy - k21);
+    const CT d12 = ALL ? g3r * ux * uy2 - k12 : c.om_3 * (g3r * ux * uy2 - k12);
+    const CT d22 = ALL ? c.c2sq * drho - k22 : c.om_4 * (c.c2sq * drho - k22);
+    const CT d2sum = d2s + d2d;
+    const CT d20 = CT(0.5) * d2sum, d20h = CT(0.25) * d2sum;
     const CT d02 = CT(0.5) * (d2s - d2d);
 
-    // f~ = f + P^-1 S^-1 F(-u) dk: y-transform back for each x-moment ...
-    CT G[3][3];  // [x-moment][e_y + 1]
-    auto yinv = [&](CT K0, CT K1, CT K2, CT *g) {
+    // f~ = f + P^-1 S^-1 F(-u) dk: y-transform back for each x-moment, giving
+    // half the result (the halves of the x-transform folded in; K0h = K0 / 2)
+    // ...
+    // (x * 0 and x + 0 are not folded away in IEEE arithmetic, so the moments
+    // known to be zero get their own forms)
+    CT G[3][3];  // [x-moment][e_y + 1], halved
+    auto yinv = [&](CT K0, CT K0h, CT K1, CT K2, CT *g) {
         const CT R1 = K1 + uy * K0;
         const CT R2 = K2 + uy * (K1 + R1);
-        const CT a = c.hinv_r * R1, b = c.hinv_r2 * R2;  // halves
+        const CT a = c.qinv_r * R1, b = c.qinv_r2 * R2;  // 1/(4r), 1/(4r^2)
         g[0] = b - a;
-        g[1] = K0 - CT(2) * b;
+        g[1] = K0h - CT(2) * b;
+        g[2] = b + a;
+    };
+    auto yinv_no0 = [&](CT K1, CT K2, CT *g) {  // K0 = 0
+        const CT R2 = K2 + uy * (K1 + K1);
+        const CT a = c.qinv_r * K1, b = c.qinv_r2 * R2;
+        g[0] = b - a;
+        g[1] = CT(-2) * b;
         g[2] = b + a;
     };
     if (FORCE) {
         // the first-order central moments change by F/gamma (k~10 = F/(2 gamma)
         // for any omega_1, since k10 = -F/(2 gamma) by the definition of u)
-        yinv(CT(0), c.fyg, d02, G[0]);
-        yinv(c.fxg, d11, d12, G[1]);
+        yinv_no0(c.fyg, d02, G[0]);
+        yinv(c.fxg, c.fxh, d11, d12, G[1]);  // fxh = fxg / 2
     } else {
-        yinv(CT(0), CT(0), d02, G[0]);
-        yinv(CT(0), d11, d12, G[1]);
+        const CT b = c.qinv_r2 * d02;  // K0 = K1 = 0
+        G[0][0] = b;
+        G[0][1] = CT(-2) * b;
+        G[0][2] = b;
+        yinv_no0(d11, d12, G[1]);
     }
-    yinv(d20, d21, d22, G[2]);
+    yinv(d20, d20h, d21, d22, G[2]);
     // ... then the x-transform back for each row, added to the populations
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
         const CT K0 = G[0][j], K1 = G[1][j], K2 = G[2][j];
         const CT R1 = K1 + ux * K0;
         const CT R2 = K2 + ux * (K1 + R1);
-        const CT h1 = CT(0.5) * R1, h2 = CT(0.5) * R2;
-        q[j][0] += h2 - h1;
-        q[j][1] += K0 - R2;
-        q[j][2] += h2 + h1;
+        q[j][0] += R2 - R1;
+        q[j][1] += CT(2) * (K0 - R2);
+        q[j][2] += R2 + R1;
     }
 #pragma unroll
     for (int a = 0; a < 9; ++a) d[a] = q[QJ[a]][QI[a]];
@@ -281,12 +298,21 @@ __device__ __forceinline__ void collide_raw(const Coef<CT> &c, CT d[9], CT gx, C
         g[1] = K0 - CT(2) * b;
         g[2] = b + a;
     };
+    auto yinv_no0 = [&](CT K1, CT K2, CT *g) {  // K0 = 0 (not folded in IEEE)
+        const CT a = c.hinv_r * K1, b = c.hinv_r2 * K2;
+        g[0] = b - a;
+        g[1] = CT(-2) * b;
+        g[2] = b + a;
+    };
     if (FORCE) {
-        yinv(CT(0), c.fyg, d02, G[0]);
+        yinv_no0(c.fyg, d02, G[0]);
         yinv(c.fxg, d11, d12, G[1]);
     } else {
-        yinv(CT(0), CT(0), d02, G[0]);
-        yinv(CT(0), d11, d12, G[1]);
+        const CT b = c.hinv_r2 * d02;  // K0 = K1 = 0
+        G[0][0] = b;
+        G[0][1] = CT(-2) * b;
+        G[0][2] = b;
+        yinv_no0(d11, d12, G[1]);
     }
     yinv(d20, d21, d22, G[2]);
     // ... then the x-transform back for each row, added to the populations

@@ -149,6 +149,16 @@ inline Coef<typename Mem<ST>::CT> coef_of(const prc_params &p)
     return make_coef<typename Mem<ST>::CT>(p, row, plane, total, (int64_t)sizeof(ST));
 }
 
+// The method as the paper runs it, for which the sweep has a specialised
+// instance: every correction, no body force, central frame, and the unit
+// rates omega_xi = omega_1 = omega_3 = omega_4 = 1 of Appendix A.
+inline bool is_plain_method(const prc_params &p)
+{
+    return p.corrections == PRC_CORR_ALL && p.fx == 0.0 && p.fy == 0.0 &&
+           p.frame == PRC_FRAME_CENTRAL && p.omega_xi == 1.0 && p.omega_1 == 1.0 &&
+           p.omega_3 == 1.0 && p.omega_4 == 1.0;
+}
+
 // blocks of the residual reduction for a grid (each block strides over the
 // nodes with gridDim * kRedBlock; the partition fixes the summation order)
 inline int red_blocks(const prc_params &p)

@@ -99,15 +99,14 @@ static prc_status launch_sweep_shape(const prc_params &p, const void *src, void 
     return PRC_OK;
 }
 
-// The method itself (every correction, no body force, central frame) runs a
-// specialised kernel; any other correction mask, a body force or the raw
-// frame runs the general one.
+// The method as the paper runs it (every correction, no body force, central
+// frame, unit non-hydrodynamic rates) runs a specialised kernel; anything
+// else runs the general one.
 template <typename ST, int BC, int TX, int TY>
 static prc_status launch_sweep_variant(const prc_params &p, const void *src, void *dst,
                                        hipStream_t s)
 {
-    if (p.corrections == PRC_CORR_ALL && p.fx == 0.0 && p.fy == 0.0 &&
-        p.frame == PRC_FRAME_CENTRAL)
+    if (is_plain_method(p))
         return launch_sweep_shape<ST, BC, TX, TY, false, true>(p, src, dst, s);
     return launch_sweep_shape<ST, BC, TX, TY, true, false>(p, src, dst, s);
 }
