@@ -15,9 +15,12 @@
  *  - Every call returns prc_status; nothing throws across the ABI.  On an
  *    error, prc_last_error() returns a message for the calling thread.
  *  - All state buffers are device memory allocated and owned by the caller;
- *    the library keeps no pointer after a call returns and allocates no
- *    device memory of its own (except the cached launch graphs of
- *    prc_step, which live until prc_release_graphs or process exit).
+ *    the single-problem calls keep no pointer after they return and allocate
+ *    no device memory of their own, except the cached launch graphs of
+ *    prc_step (until prc_release_graphs or process exit) and the scratch
+ *    states prc_tune allocates and frees within the call.  A batch owns its
+ *    small tables and graphs until prc_batch_destroy; prc_serve allocates its
+ *    request pool for the duration of the call.
  *  - Calls are ordered on the HIP stream passed in (0 = null stream) and are
  *    asynchronous unless stated otherwise.
  *  - Arguments are validated on the host before anything is launched;

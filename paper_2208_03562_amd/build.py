@@ -44,9 +44,15 @@ if __name__ == "__main__":
 
 
 def source_hash() -> str:
-    """Hash of the library's sources (identifies the kernel a profile was taken on)."""
+    """Hash of the library's code (identifies the kernels a profile was taken
+    on): the sources and headers with comments and blank space removed, so
+    that editing a comment does not orphan the committed counter data."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in sorted(SOURCES + HEADERS):
-        h.update(open(f, "rb").read())
+        text = open(f, encoding="utf-8").read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]

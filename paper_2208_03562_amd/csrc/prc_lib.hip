@@ -1,12 +1,15 @@
-// C ABI and kernels of the PRC-LBM library for MI355X (gfx950).
+// C ABI of the PRC-LBM library for MI355X (gfx950): single problems.
 //
-// Kernels:
+// Kernels launched here:
 //   k_sweep     one fused time step: pull with boundaries, fields, density
 //               gradient from an LDS tile of densities, collision, store
+//               (prc_sweep.hpp, prc_collide.hpp)
 //   k_macros    fields of a state (for output)
 //   k_residual  per-block FP64 partial sums of the convergence check
-//   k_finish    fixed-order reduction of the partial sums
-// The ABI is declared and documented in include/prc.h.
+//   k_finish    fixed-order reduction of the partial sums (prc_reduce.hpp)
+//   k_zero      rest state
+// Batches are in prc_batch.hip, the request server in prc_serve.hip.  The
+// ABI is declared and documented in include/prc.h.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
