@@ -197,3 +197,37 @@ def test_serve_rejects_unordered_arrivals():
 
 def test_serve_empty_trace_is_a_no_op():
     assert capi.prc_serve(serve_cfg(), []) == []
+
+
+def test_state_size_limit_is_4_gib():
+    """Byte offsets into a state are 32-bit: the largest accepted state is the
+    last that fits 4 GiB, one more row is rejected."""
+    p = base()
+    p.nx, p.storage = 16384, capi.PRC_F32
+    row, _ = capi.prc_layout(p)
+    ny_max = (2 ** 32 - 1) // (row * 4)
+    p.ny = ny_max
+    assert capi.prc_state_bytes(p) <= 2 ** 32 - 1
+    p.ny = ny_max + 1
+    with pytest.raises(capi.PrcError):
+        capi.prc_validate(p)
+
+
+@pytest.mark.parametrize("kw", [dict(check_every=0), dict(max_steps=-1),
+                                dict(tol=-1.0), dict(tol=float("nan"))])
+def test_solve_rejects_bad_arguments_before_launching(kw):
+    p = base()
+    args = dict(tol=1e-6, check_every=100, max_steps=1000)
+    args.update(kw)
+    with pytest.raises(capi.PrcError) as e:
+        capi.prc_solve(p, 256 * 1000, 256 * 2000, 256 * 3000, 256 * 4000, args["tol"],
+                       args["check_every"], args["max_steps"])
+    assert e.value.status == capi.PRC_EINVAL
+
+
+@pytest.mark.parametrize("a,b,n", [(0, 256 * 2000, 1), (256 * 1000, 256 * 1000, 1),
+                                   (256 * 1000 + 4, 256 * 2000, 1), (256 * 1000, 256 * 2000, -1)])
+def test_step_rejects_bad_buffers_before_launching(a, b, n):
+    with pytest.raises(capi.PrcError) as e:
+        capi.prc_step(base(), a, b, n)
+    assert e.value.status == capi.PRC_EINVAL

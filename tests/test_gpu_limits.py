@@ -1,0 +1,79 @@
+"""Sizes at the limits: the 4096 x 2048 grid of the 16-bit workload against
+the oracle at every node, the largest state the library accepts (4 GiB of
+FP32, the top rows at the highest 32-bit offsets), and zero steps."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from tests.common import lib_params, max_rel_velocity_error, oracle_deviation, oracle_params, spec
+
+pytestmark = pytest.mark.gpu
+
+ROUND = {"f32": lambda a: a.astype(np.float32).astype(np.float64),
+         "f16": lambda a: torch.from_numpy(a).to(torch.float16).double().numpy(),
+         "bf16": lambda a: torch.from_numpy(a).to(torch.bfloat16).double().numpy()}
+ONE_STEP_BOUND = {"f32": 1e-5, "f16": 2e-3, "bf16": 1.6e-2}
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_4096x2048_one_step_every_node(O, storage):
+    """The full-size shallow cavity (r 0.5, gamma 0.05, Ma 0.02 lid), launched
+    as the benchmark launches it, one step from a seeded random state."""
+    w = workloads.CAVITY_4096x2048_MA002[storage]
+    s = spec(w.nx, w.ny, w.r, w.gamma, re=w.re, omega_nu=None, u_lid=w.u_lid, storage=storage)
+    from paper_2208_03562_amd import solver
+    sol = solver.Solver(lib_params(s))
+    noise = ROUND[storage](workloads.deviation_noise(w.nx, w.ny, seed=4096, amplitude=1e-3))
+    sol.set_state(noise)
+    po = oracle_params(O, s)
+    ft = np.ascontiguousarray(O.rest_state(po) + noise)
+    del noise
+    sol.step(1)
+    O.step(po, ft, 1)
+    dev = oracle_deviation(O, po, ft)
+    got = sol.get_state().cpu().numpy()
+    err = np.abs(got - dev).max() / np.abs(dev).max()
+    assert err < ONE_STEP_BOUND[storage], err
+
+
+def test_largest_state_corners_match_a_small_cavity(O):
+    """The largest FP32 state (16384 x ny_max nodes, just under 4 GiB): after
+    k steps from rest a node depends only on nodes within 2k of it (one link
+    of streaming and one of the density gradient per step), so the top
+    corners of this grid must equal those of a 64 x 64 cavity with the same
+    parameters.  The top-right corner sits at the highest byte offsets."""
+    from paper_2208_03562_amd import capi, solver
+    k, m = 10, 20
+    nx = 16384
+    probe = lib_params(spec(nx, 64, 2.0, 0.5, omega_nu=1.6, u_lid=0.05))
+    row, _ = capi.prc_layout(probe)
+    ny = (2 ** 32 - 1) // (row * 4)
+    big = spec(nx, ny, 2.0, 0.5, omega_nu=1.6, u_lid=0.05)
+    small = spec(64, 64, 2.0, 0.5, omega_nu=1.6, u_lid=0.05)
+    sol = solver.Solver(lib_params(big))
+    assert capi.prc_state_bytes(sol.p) > 4.2e9
+    sol.step(k)
+    _, ux, uy = sol.macros()
+    po = oracle_params(O, small)
+    ft = O.rest_state(po)
+    O.step(po, ft, k)
+    _, oux, ouy = O.velocity(po, ft)
+    for big_cols, small_cols in ((slice(0, m), slice(0, m)),
+                                 (slice(nx - m, nx), slice(64 - m, 64))):
+        a = ux[ny - m:, big_cols].cpu().numpy(), uy[ny - m:, big_cols].cpu().numpy()
+        b = oux[64 - m:, small_cols], ouy[64 - m:, small_cols]
+        assert max_rel_velocity_error(a[0], a[1], b[0], b[1], 0.05) < 1e-5
+    # and the far interior is still at rest
+    assert float(ux[ny // 2, nx // 2]) == 0.0 and float(uy[ny // 2, nx // 2]) == 0.0
+
+
+def test_zero_steps_change_nothing(O):
+    from paper_2208_03562_amd import solver
+    s = spec(70, 30, 2.0, 0.5, omega_nu=1.2, u_lid=0.03, storage="f64")
+    sol = solver.Solver(lib_params(s))
+    noise = workloads.deviation_noise(70, 30, seed=3, amplitude=1e-3)
+    sol.set_state(noise)
+    before = sol.get_state().clone()
+    sol.step(0)
+    assert bool((sol.get_state() == before).all())
