@@ -296,44 +296,51 @@ def traffic_from_counters(pmc_dir: str):
     """Write profiles/traffic.json from two rocprofv3 --pmc runs of
     `bench.py --pmc-run N` (pmc_dir/FETCH_SIZE and pmc_dir/WRITE_SIZE, CSV
     output named run_*).  Each counter is scaled by what it reads for the
-    256 MiB copy, then averaged over the sweep dispatches of each grid (the
-    kernel instance dispatched most often on that grid: the tuned tile)."""
+    256 MiB copy and averaged over the dispatches of each sweep instance on
+    each grid (the tuner dispatches every tile shape, so every instance the
+    benchmark may pick is covered); bytes per launch, per grid and instance."""
     import collections
     import csv
 
     from paper_2208_03562_amd import build
 
-    rec = {"source_hash": build.source_hash(), "copy_scale": {}, "kib_per_dispatch": {},
-           "note": "bytes per launch of k_sweep: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) "
-                   "each scaled by its reading for a 256 MiB device copy"}
-    per = {}
+    rec = {"source_hash": build.source_hash(), "copy_scale": {}, "bytes_per_launch": {},
+           "note": "HBM bytes per launch of each sweep instance: FETCH_SIZE and WRITE_SIZE "
+                   "(KiB per dispatch) each scaled by its reading for a 256 MiB device copy"}
+    per = collections.defaultdict(lambda: collections.defaultdict(float))
     for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
         rows = list(csv.DictReader(open(os.path.join(pmc_dir, ctr, "run_counter_collection.csv"))))
         copy = [(int(r["Grid_Size"]), float(r["Counter_Value"])) for r in rows
                 if "copyBuffer" in r["Kernel_Name"] and r["Counter_Name"] == ctr]
         big = max(g for g, _ in copy)
         copy = [v for g, v in copy if g == big]
-        copy_kib = sum(copy) / len(copy)
-        scale = PMC_COPY_BYTES / (copy_kib * 1024.0)
+        scale = PMC_COPY_BYTES / (sum(copy) / len(copy) * 1024.0)
         rec["copy_scale"][ctr] = round(scale, 5)
         for w in PMC_GRIDS:
             groups = collections.defaultdict(list)
             for r in rows:
                 if ("k_sweep" in r["Kernel_Name"] and r["Counter_Name"] == ctr
                         and int(r["Grid_Size"]) == w.nx * w.ny):
-                    groups[r["Kernel_Name"]].append(float(r["Counter_Value"]))
-            name, vals = max(groups.items(), key=lambda kv: len(kv[1]))
-            kib = sum(vals) / len(vals)
-            rec["kib_per_dispatch"].setdefault(w.name, {})[ctr] = round(kib, 3)
-            rec["kib_per_dispatch"][w.name]["kernel"] = name.split("(")[0].replace("void ", "")
-            rec["kib_per_dispatch"][w.name]["dispatches"] = len(vals)
-            per[w.name] = per.get(w.name, 0.0) + kib * 1024.0 * scale
-    for k, v in per.items():
-        rec[k] = int(round(v))
+                    groups[r["Kernel_Name"].split("(")[0].replace("void ", "")].append(
+                        float(r["Counter_Value"]))
+            for name, vals in groups.items():
+                per[w.name][name] += sum(vals) / len(vals) * 1024.0 * scale
+    for wname, kernels in per.items():
+        rec["bytes_per_launch"][wname] = {k: int(round(v)) for k, v in sorted(kernels.items())}
     path = os.path.join(ROOT, "profiles", "traffic.json")
     with open(path, "w") as fh:
         json.dump(rec, fh, indent=1)
     print(json.dumps(rec))
+
+
+def sweep_kernel_name(storage: str, bc: int, tile: int) -> str:
+    """Demangled name of the sweep instance bench.py runs (the method as the
+    paper runs it) for a storage type, boundary type and tile index."""
+    from paper_2208_03562_amd import capi
+    tx, ty, steps = capi.prc_tile_info(tile)
+    ctype = {"f64": "double", "f32": "float", "f16": "__half", "bf16": "__hip_bfloat16"}[storage]
+    kern = "k_sweep2" if steps == 2 else "k_sweep"
+    return f"prc::{kern}<{ctype}, {bc}, {tx}, {ty}, false, true>"
 
 
 def trace_summary(trace_dir: str):
@@ -358,9 +365,10 @@ def trace_summary(trace_dir: str):
               f"{v[len(v) // 2] / 1e3:.3f} | {v[0] / 1e3:.3f} |")
 
 
-def measured_traffic(w: workloads.Cavity):
-    """HBM bytes per launch of the sweep from the committed counter summary,
-    if it was taken on the current kernel sources (else None)."""
+def measured_traffic(w: workloads.Cavity, kernel: str):
+    """HBM bytes per launch of sweep instance `kernel` on grid w from the
+    committed counter summary, if it was taken on the current library code
+    (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         rec = json.load(open(path))
@@ -369,7 +377,7 @@ def measured_traffic(w: workloads.Cavity):
     from paper_2208_03562_amd import build
     if rec.get("source_hash") != build.source_hash():
         return None
-    return rec.get(w.name)
+    return rec.get("bytes_per_launch", {}).get(w.name, {}).get(kernel)
 
 
 def main():
@@ -406,6 +414,7 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    from paper_2208_03562_amd import capi
     if args.pmc_run > 0:
         pmc_run(args.pmc_run)
         return
@@ -423,6 +432,7 @@ def main():
             big[wh.name] = dict(
                 workload=wh.name, u_lid=round(wh.u_lid, 6), mlups=round(r["mlups"], 1),
                 sweep_us=round(r["sweep_us"], 2), achieved_gbs=round(r["sweep_gbs"], 1),
+                tile=r["tile"], steps_per_launch=capi.prc_tile_info(r["tile"])[2],
                 frac=round(r["sweep_gbs"] / HBM_PEAK_GBS, 4),
                 bytes_per_node=BYTES_PER_NODE[wh.storage], diverged_at_step=r["diverged_at"])
     batch = run_batch(args.batch_instances, 16) if args.batch_instances > 0 else None
@@ -431,7 +441,10 @@ def main():
              if args.serve_requests > 0 else None)
     parity = oracle_parity(w, wc) if args.cpu_budget > 0 else None
     cpu = run_cpu_baseline(w, args.cpu_budget) if args.cpu_budget > 0 else None
-    traffic = measured_traffic(w)
+    _, _, per_launch = capi.prc_tile_info(main_res["tile"])
+    kernel = sweep_kernel_name(w.storage, 0, main_res["tile"])
+    traffic = measured_traffic(w, kernel)
+    nodes = w.nx * w.ny
 
     out = {
         "metric": "MLUPS",
@@ -453,11 +466,15 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(main_res["sweep_gbs"] / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "traffic_unit": "bytes per launch",
-                     "algorithmic_bytes": BYTES_PER_NODE[w.storage] * w.nx * w.ny,
-                     "kernel": "k_sweep",
-                     "kernel_us": round(main_res["sweep_us"], 3),
-                     "note": "72 B/node (9 FP32 reads + 9 FP32 writes) x 524288 nodes per launch; "
-                             "the 37.7 MB working set stays in the last-level cache"},
+                     "algorithmic_bytes": BYTES_PER_NODE[w.storage] * nodes * per_launch,
+                     "kernel": kernel,
+                     "steps_per_launch": per_launch,
+                     "kernel_us": round(main_res["sweep_us"] * per_launch, 3),
+                     "note": f"72 B per node update (9 FP32 reads + 9 FP32 writes) x {nodes} "
+                             f"nodes x {per_launch} step(s) per launch; achieved = those bytes / "
+                             "launch time.  A two-step launch keeps the intermediate state in "
+                             "LDS, so it moves fewer bytes than that (traffic); the 37.7 MB "
+                             "state stays in the last-level cache"},
         "solution": {"diverged_at_step": main_res["diverged_at"],
                      "residual_last": main_res["residual_last"],
                      "note": "U = 0.05 with gamma = 0.1 is outside the scheme's stable range; "

@@ -177,10 +177,12 @@ prc_status prc_solve(const prc_params *p, void *f_a, void *f_b, double *u_prev,
                      int64_t hist_cap, int64_t *hist_len, hipStream_t stream);
 
 /* Autotuner: time every tile shape of the sweep kernel (threads along x by
- * along y: 0 = 64 x 4, 1 = 64 x 8, 2 = 128 x 4, 3 = 32 x 8, 4 = 32 x 16) for
- * this problem's storage,
+ * along y: 0 = 64 x 4, 1 = 64 x 8, 2 = 128 x 4, 3 = 32 x 8, 4 = 32 x 16, one
+ * time step per launch; 5 = 64 x 8, 6 = 32 x 16, 7 = 64 x 16, 8 = 32 x 32, two
+ * time steps per launch with the intermediate state in LDS, FP32 and 16-bit
+ * storage only; see prc_tile_info) for this problem's storage,
  * boundaries and grid size, on two scratch state buffers that the call
- * allocates and frees itself (hipMalloc/hipFree), and use the fastest for
+ * allocates and frees itself (hipMalloc/hipFree), and use the fastest (per time step) for
  * every later sweep of a problem with the same storage, boundaries and grid
  * size in this process.  The tile shape changes only the speed, not the
  * results.  tile_out (host, may be NULL) receives the chosen index.  Without
@@ -188,6 +190,13 @@ prc_status prc_solve(const prc_params *p, void *f_a, void *f_b, double *u_prev,
  * and 64 x 4 otherwise.  Synchronises the stream; PRC_EHIP if the scratch
  * allocation fails. */
 prc_status prc_tune(const prc_params *p, int32_t *tile_out, hipStream_t stream);
+
+/* Shape of tile index `tile` (0 .. 8): threads along x and y and time steps
+ * per launch.  A two-step launch computes the intermediate step on the tile
+ * plus two rings in LDS (temporal blocking, for states that fit the cache or
+ * to halve the state traffic); its results are bit for bit those of two
+ * single steps.  Any output pointer may be NULL.  Host only. */
+prc_status prc_tile_info(int32_t tile, int32_t *tx, int32_t *ty, int32_t *steps);
 
 /* Use tile shape `tile` (index as for prc_tune; -1 forgets any choice) for
  * problems with this storage, boundaries and grid size.  Host only; does not

@@ -11,7 +11,7 @@ LIB = os.path.join(PKG, "libprc.so")
 SOURCES = [os.path.join(CSRC, f) for f in ("prc_lib.hip", "prc_batch.hip", "prc_serve.hip")]
 HEADERS = [os.path.join(CSRC, h) for h in ("prc_coef.hpp", "prc_device.hpp", "prc_collide.hpp",
                                          "prc_sweep.hpp", "prc_host.hpp", "prc_reduce.hpp",
-                                         "prc_batch.hpp")] + [
+                                         "prc_batch.hpp", "prc_sweep2.hpp")] + [
     os.path.join(ROOT, "include", "prc.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

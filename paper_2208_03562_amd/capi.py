@@ -98,6 +98,9 @@ _PROTOS = {
                                  ctypes.c_int64, _I64P, _VP]),
     "prc_tune": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), _VP]),
     "prc_set_tile": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "prc_tile_info": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int32)]),
     "prc_release_graphs": (ctypes.c_int, []),
     "prc_last_error": (ctypes.c_char_p, []),
     "prc_batch_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_VP)]),
@@ -235,6 +238,14 @@ def prc_tune(p: prc_params, stream: int = 0) -> int:
     t = ctypes.c_int32(-1)
     _check("prc_tune", lib().prc_tune(ctypes.byref(p), ctypes.byref(t), stream))
     return t.value
+
+
+def prc_tile_info(tile: int):
+    """(threads along x, threads along y, time steps per launch) of a tile index."""
+    tx, ty, st = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check("prc_tile_info", lib().prc_tile_info(int(tile), ctypes.byref(tx), ctypes.byref(ty),
+                                                ctypes.byref(st)))
+    return tx.value, ty.value, st.value
 
 
 def prc_set_tile(p: prc_params, tile: int) -> None:

@@ -586,7 +586,7 @@ prc_status prc_batch_tune(prc_batch *b, int32_t *tile_out, hipStream_t stream)
     float best_ms = 0.0f;
     hipError_t he = hipEventCreate(&e0);
     if (he == hipSuccess) he = hipEventCreate(&e1);
-    for (int t = 0; t < kNumTiles && he == hipSuccess && st == PRC_OK; ++t) {
+    for (int t = 0; t < kNumSingleStepTiles && he == hipSuccess && st == PRC_OK; ++t) {
         b->tile = t;
         b->dirty = true;
         if ((st = ensure_tables(*b, stream)) != PRC_OK) break;
@@ -620,7 +620,9 @@ prc_status prc_batch_set_tile(prc_batch *b, int32_t tile)
 {
     prc_status st = batch_ok(b);
     if (st != PRC_OK) return st;
-    if (tile < 0 || tile >= kNumTiles) return fail(PRC_EINVAL, "tile %d out of range", tile);
+    if (tile < 0 || tile >= kNumSingleStepTiles)
+        return fail(PRC_EINVAL, "tile %d out of range for a batch (0 .. %d)", tile,
+                    kNumSingleStepTiles - 1);
     if (tile != b->tile) {
         b->tile = tile;
         b->dirty = true;

@@ -172,11 +172,23 @@ inline int red_blocks(const prc_params &p)
 // ring densities per node; a wider one gives longer contiguous row segments.
 struct TileShape {
     int tx, ty;
+    int steps;  // time steps per launch: 1 (k_sweep) or 2 (k_sweep2)
 };
 // Narrow shapes waste fewer threads on grids whose width is not a multiple
 // of 64 (batches of small problems); a wavefront then spans two or four rows.
-constexpr TileShape kTiles[] = {{64, 4}, {64, 8}, {128, 4}, {32, 8}, {32, 16}};
+// The two-step shapes (FP32 and 16-bit storage, single problems) trade the
+// collisions of two extra rings per tile for half the state traffic and half
+// the launches; squarer tiles have relatively smaller rings.
+constexpr TileShape kTiles[] = {{64, 4, 1},  {64, 8, 1},  {128, 4, 1}, {32, 8, 1}, {32, 16, 1},
+                                {64, 8, 2},  {32, 16, 2}, {64, 16, 2}, {32, 32, 2}};
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
+constexpr int kNumSingleStepTiles = 5;  // indices below this advance one step
+
+// Whether tile shape `tile` may run problem p (two-step shapes: no FP64).
+inline bool tile_allowed(const prc_params &p, int tile)
+{
+    return tile >= 0 && tile < kNumTiles && (kTiles[tile].steps == 1 || p.storage != PRC_F64);
+}
 
 // run F<ST, BC>(args...) for the storage and boundary type of p
 #define PRC_DISPATCH(p, FN, ...)                                                          \
@@ -198,8 +210,9 @@ constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
         return fail(PRC_EINVAL, "bad storage/bc");                                       \
     }()
 
-// Sweeps per captured launch graph (an even count, so that the newest state
-// is back in the first buffer after every replay).
+// Steps per captured launch graph (a multiple of four, so that the newest
+// state is back in the first buffer after every replay for one- and
+// two-step launches alike).
 constexpr int kGraphStepsDefault = 64;
 
 // sweeps per graph; PRC_GRAPH_STEPS overrides (0 disables graphs)
@@ -209,7 +222,7 @@ inline int graph_steps()
         const char *e = std::getenv("PRC_GRAPH_STEPS");
         if (!e) return kGraphStepsDefault;
         const int n = std::atoi(e);
-        return n <= 0 ? 0 : (n + 1) / 2 * 2;
+        return n <= 0 ? 0 : (n + 3) / 4 * 4;
     }();
     return v;
 }

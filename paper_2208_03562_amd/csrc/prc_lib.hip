@@ -29,6 +29,7 @@
 #include "prc_host.hpp"
 #include "prc_reduce.hpp"
 #include "prc_sweep.hpp"
+#include "prc_sweep2.hpp"
 
 namespace prc {
 
@@ -79,16 +80,20 @@ static int tile_choice(const prc_params &p)
         const int i = e ? std::atoi(e) : -1;
         return (i >= 0 && i < kNumTiles) ? i : -1;
     }();
-    if (forced >= 0) return forced;
+    if (forced >= 0 && tile_allowed(p, forced)) return forced;
     {
         std::lock_guard<std::mutex> lock(g_tune_mu);
         auto it = g_tuned.find(tune_key(p));
         if (it != g_tuned.end()) return it->second;
     }
+    // measured on MI355X: two steps per launch pays for FP32 on grids that
+    // fill the chip; 16-bit storage is bound by arithmetic, where the extra
+    // ring collisions of the two-step shapes cost more than they save
+    if (p.storage == PRC_F32 && p.nx >= 256 && p.ny >= 64) return 8;
     return p.nx >= 256 ? 2 : 0;
 }
 
-template <typename ST, int BC, int TX, int TY, bool FORCE, bool ALL>
+template <typename ST, int BC, int TX, int TY, bool FORCE, bool ALL, int STEPS>
 static prc_status launch_sweep_shape(const prc_params &p, const void *src, void *dst, hipStream_t s)
 {
     auto c = coef_of<ST>(p);
@@ -96,8 +101,17 @@ static prc_status launch_sweep_shape(const prc_params &p, const void *src, void 
     c.tiles_y = (p.ny + TY - 1) / TY;
     const int tiles = c.tiles_x * c.tiles_y;
     c.tiles_per_xcd = (tiles + kXcds - 1) / kXcds;
-    hipLaunchKernelGGL((k_sweep<ST, BC, TX, TY, FORCE, ALL>), dim3(c.tiles_per_xcd * kXcds),
-                       dim3(TX * TY), 0, s, (const ST *)src, (ST *)dst, c);
+    if constexpr (STEPS == 2) {
+        if constexpr (sizeof(ST) <= 4)
+            hipLaunchKernelGGL((k_sweep2<ST, BC, TX, TY, FORCE, ALL>),
+                               dim3(c.tiles_per_xcd * kXcds), dim3(TX * TY), 0, s,
+                               (const ST *)src, (ST *)dst, c);
+        else
+            return fail(PRC_EINVAL, "two-step sweep shapes need FP32 or 16-bit storage");
+    } else {
+        hipLaunchKernelGGL((k_sweep<ST, BC, TX, TY, FORCE, ALL>), dim3(c.tiles_per_xcd * kXcds),
+                           dim3(TX * TY), 0, s, (const ST *)src, (ST *)dst, c);
+    }
     HIP_TRY(hipGetLastError());
     return PRC_OK;
 }
@@ -105,15 +119,16 @@ static prc_status launch_sweep_shape(const prc_params &p, const void *src, void 
 // The method as the paper runs it (every correction, no body force, central
 // frame, unit non-hydrodynamic rates) runs a specialised kernel; anything
 // else runs the general one.
-template <typename ST, int BC, int TX, int TY>
+template <typename ST, int BC, int TX, int TY, int STEPS = 1>
 static prc_status launch_sweep_variant(const prc_params &p, const void *src, void *dst,
                                        hipStream_t s)
 {
     if (is_plain_method(p))
-        return launch_sweep_shape<ST, BC, TX, TY, false, true>(p, src, dst, s);
-    return launch_sweep_shape<ST, BC, TX, TY, true, false>(p, src, dst, s);
+        return launch_sweep_shape<ST, BC, TX, TY, false, true, STEPS>(p, src, dst, s);
+    return launch_sweep_shape<ST, BC, TX, TY, true, false, STEPS>(p, src, dst, s);
 }
 
+// One launch of tile shape `tile`: kTiles[tile].steps time steps, src -> dst.
 template <typename ST, int BC>
 static prc_status launch_sweep_tile(const prc_params &p, int tile, const void *src, void *dst,
                                     hipStream_t s)
@@ -123,14 +138,48 @@ static prc_status launch_sweep_tile(const prc_params &p, int tile, const void *s
     case 2: return launch_sweep_variant<ST, BC, 128, 4>(p, src, dst, s);
     case 3: return launch_sweep_variant<ST, BC, 32, 8>(p, src, dst, s);
     case 4: return launch_sweep_variant<ST, BC, 32, 16>(p, src, dst, s);
+    case 5: return launch_sweep_variant<ST, BC, 64, 8, 2>(p, src, dst, s);
+    case 6: return launch_sweep_variant<ST, BC, 32, 16, 2>(p, src, dst, s);
+    case 7: return launch_sweep_variant<ST, BC, 64, 16, 2>(p, src, dst, s);
+    case 8: return launch_sweep_variant<ST, BC, 32, 32, 2>(p, src, dst, s);
     default: return launch_sweep_variant<ST, BC, 64, 4>(p, src, dst, s);
     }
 }
 
-template <typename ST, int BC>
-static prc_status launch_sweep(const prc_params &p, const void *src, void *dst, hipStream_t s)
+// The single-step shape used next to a two-step one for the odd steps.
+static int single_step_tile(int tile)
 {
-    return launch_sweep_tile<ST, BC>(p, tile_choice(p), src, dst, s);
+    return kTiles[tile].steps == 1 ? tile : (kTiles[tile].tx >= 64 ? 1 : 4);
+}
+
+// Launch sequence for steps [k0, k0 + n) from buffers (f_a, f_b): step k reads
+// f_a when k is even.  A two-step launch moves the state across one buffer
+// flip for two steps, so pairs of them (f_a -> f_b -> f_a) cover the steps in
+// fours from an even step and leave every state a caller can see on the
+// buffer the single-step sequence puts it in; single steps do the rest.
+static prc_status run_steps(const prc_params &p, int tile, void *f_a, void *f_b, int64_t k0,
+                            int64_t n, hipStream_t s)
+{
+    prc_status st = PRC_OK;
+    int64_t k = k0;
+    const int64_t end = k0 + n;
+    const int one = single_step_tile(tile);
+    auto single = [&]() {
+        const void *src = (k & 1) ? f_b : f_a;
+        void *dst = (k & 1) ? f_a : f_b;
+        ++k;
+        return PRC_DISPATCH(p, launch_sweep_tile, p, one, src, dst, s);
+    };
+    if (kTiles[tile].steps == 2) {
+        if (k < end && (k & 1)) st = single();
+        for (; k + 4 <= end && st == PRC_OK; k += 4) {
+            // steps k, k+1: f_a -> f_b; steps k+2, k+3: f_b -> f_a
+            st = PRC_DISPATCH(p, launch_sweep_tile, p, tile, f_a, f_b, s);
+            if (st == PRC_OK) st = PRC_DISPATCH(p, launch_sweep_tile, p, tile, f_b, f_a, s);
+        }
+    }
+    while (k < end && st == PRC_OK) st = single();
+    return st;
 }
 
 template <typename ST, int BC>
@@ -183,12 +232,13 @@ static void destroy_graphs_locked()
     g_graphs.clear();
 }
 
-static prc_status get_graph(const prc_params &p, void *f_a, void *f_b, int nsteps,
+static prc_status get_graph(const prc_params &p, int tile, void *f_a, void *f_b, int nsteps,
                             hipGraphExec_t *out)
 {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     std::string key(reinterpret_cast<const char *>(&p), sizeof p);
+    key.append(reinterpret_cast<const char *>(&tile), sizeof tile);
     key.append(reinterpret_cast<const char *>(&f_a), sizeof f_a);
     key.append(reinterpret_cast<const char *>(&f_b), sizeof f_b);
     key.append(reinterpret_cast<const char *>(&dev), sizeof dev);
@@ -205,11 +255,7 @@ static prc_status get_graph(const prc_params &p, void *f_a, void *f_b, int nstep
     prc_status st = PRC_OK;
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        for (int k = 0; k < nsteps && st == PRC_OK; ++k) {
-            const void *src = (k & 1) ? f_b : f_a;
-            void *dst = (k & 1) ? f_a : f_b;
-            st = PRC_DISPATCH(p, launch_sweep, p, src, dst, cs);
-        }
+        st = run_steps(p, tile, f_a, f_b, 0, nsteps, cs);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(cs, &g);
         if (e == hipSuccess && st == PRC_OK) {
@@ -315,24 +361,20 @@ prc_status prc_step(const prc_params *p, void *f_a, void *f_b, int64_t nsteps, h
     if (f_a == f_b) return fail(PRC_EINVAL, "f_a and f_b must be distinct buffers");
     if (nsteps < 0) return fail(PRC_EINVAL, "nsteps < 0");
     int64_t k = 0;
-    // Long runs replay a captured graph of kGraphSteps sweeps (an even count,
-    // so the newest state is back in f_a after every replay).  Not while the
-    // caller's stream is itself being captured.
+    const int tile = tile_choice(*p);
+    // Long runs replay a captured graph of graph_steps() steps (a multiple of
+    // four, so the newest state is back in f_a after every replay whether the
+    // shape takes one or two steps per launch).  Not while the caller's stream
+    // is itself being captured.
     const int gsteps = graph_steps();
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     HIP_TRY(hipStreamIsCapturing(stream, &cap));
     if (gsteps > 0 && cap == hipStreamCaptureStatusNone && nsteps >= 2 * gsteps) {
         hipGraphExec_t exec = nullptr;
-        if ((st = get_graph(*p, f_a, f_b, gsteps, &exec)) != PRC_OK) return st;
+        if ((st = get_graph(*p, tile, f_a, f_b, gsteps, &exec)) != PRC_OK) return st;
         for (; k + gsteps <= nsteps; k += gsteps) HIP_TRY(hipGraphLaunch(exec, stream));
     }
-    for (; k < nsteps; ++k) {
-        const void *src = (k & 1) ? f_b : f_a;
-        void *dst = (k & 1) ? f_a : f_b;
-        st = PRC_DISPATCH(*p, launch_sweep, *p, src, dst, stream);
-        if (st != PRC_OK) return st;
-    }
-    return PRC_OK;
+    return run_steps(*p, tile, f_a, f_b, k, nsteps - k, stream);
 }
 
 prc_status prc_residual(const prc_params *p, const void *f, double *u_prev, void *scratch,
@@ -424,6 +466,7 @@ prc_status prc_tune(const prc_params *p, int32_t *tile_out, hipStream_t stream)
     if (he == hipSuccess) he = hipEventCreate(&e0);
     if (he == hipSuccess) he = hipEventCreate(&e1);
     for (int t = 0; t < kNumTiles && he == hipSuccess && st == PRC_OK; ++t) {
+        if (!tile_allowed(*p, t)) continue;
         for (int k = 0; k < kWarm + kTimed && st == PRC_OK; ++k) {
             if (k == kWarm) he = hipEventRecord(e0, stream);
             st = PRC_DISPATCH(*p, launch_sweep_tile, *p, t, (k & 1) ? b : a, (k & 1) ? a : b,
@@ -434,6 +477,7 @@ prc_status prc_tune(const prc_params *p, int32_t *tile_out, hipStream_t stream)
         if (he == hipSuccess) he = hipEventSynchronize(e1);
         float ms = 0.0f;
         if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        ms /= (float)kTiles[t].steps;  // per time step
         if (he == hipSuccess && (best < 0 || ms < best_ms)) {
             best = t;
             best_ms = ms;
@@ -453,11 +497,22 @@ prc_status prc_tune(const prc_params *p, int32_t *tile_out, hipStream_t stream)
     return PRC_OK;
 }
 
+prc_status prc_tile_info(int32_t tile, int32_t *tx, int32_t *ty, int32_t *steps)
+{
+    if (tile < 0 || tile >= kNumTiles) return fail(PRC_EINVAL, "tile %d out of range", tile);
+    if (tx) *tx = kTiles[tile].tx;
+    if (ty) *ty = kTiles[tile].ty;
+    if (steps) *steps = kTiles[tile].steps;
+    return PRC_OK;
+}
+
 prc_status prc_set_tile(const prc_params *p, int32_t tile)
 {
     prc_status st = validate(p);
     if (st != PRC_OK) return st;
     if (tile < -1 || tile >= kNumTiles) return fail(PRC_EINVAL, "tile %d out of range", tile);
+    if (tile >= 0 && !tile_allowed(*p, tile))
+        return fail(PRC_EINVAL, "tile %d (two steps per launch) needs FP32 or 16-bit storage", tile);
     std::lock_guard<std::mutex> lock(g_tune_mu);
     if (tile < 0)
         g_tuned.erase(tune_key(*p));

@@ -69,6 +69,36 @@ __device__ __forceinline__ void tile_densities(CT (*srho)[TX + 2], const TileGeo
     if (g.ring) srho[g.hy + 1][g.hx + 1] = sum9(e);
 }
 
+// Density gradient at LDS position (lx, ly) of a density tile: rest-weighted
+// central differences over the eight neighbours (exact for linear rho; the
+// [4,1,1]/12 stencil at r = 1).
+template <typename CT, int W>
+__device__ __forceinline__ void density_gradient(const Coef<CT> &c, const CT (*D)[W], int lx,
+                                                 int ly, CT &gx, CT &gy)
+{
+    const CT rE = D[ly][lx + 1], rW = D[ly][lx - 1];
+    const CT rN = D[ly + 1][lx], rS = D[ly - 1][lx];
+    const CT rNE = D[ly + 1][lx + 1], rNW = D[ly + 1][lx - 1];
+    const CT rSE = D[ly - 1][lx + 1], rSW = D[ly - 1][lx - 1];
+    gx = c.gxa * (rE - rW) + c.gxb * ((rNE - rNW) + (rSE - rSW));
+    gy = c.gya * (rN - rS) + c.gyb * ((rNE + rNW) - (rSE + rSW));
+}
+
+// The collision of one node: the specialised central-moment update, or in
+// the general instance the frame read at run time.
+template <typename CT, bool FORCE, bool ALL>
+__device__ __forceinline__ void collide_node(const Coef<CT> &c, CT d[9], CT gx, CT gy)
+{
+    if constexpr (ALL) {
+        collide<CT, FORCE, ALL>(c, d, gx, gy);
+    } else {
+        if (c.frame == PRC_FRAME_RAW)
+            collide_raw<CT, FORCE>(c, d, gx, gy);
+        else
+            collide<CT, FORCE, ALL>(c, d, gx, gy);
+    }
+}
+
 // Density gradient, collision and store of this thread's node (after the
 // barrier that publishes the LDS densities).
 template <typename ST, int TX, int TY, bool FORCE, bool ALL>
@@ -81,24 +111,9 @@ __device__ __forceinline__ void tile_finish(const Coef<typename Mem<ST>::CT> &c,
     constexpr uint32_t E = sizeof(ST);
     const int x = x0 + g.tx, y = y0 + g.ty;
     if (x >= c.nx || y >= c.ny) return;
-    // rest-weighted central differences over the eight neighbours (exact for
-    // linear rho; the [4,1,1]/12 stencil at r = 1)
-    const int lx = g.tx + 1, ly = g.ty + 1;
-    const CT rE = srho[ly][lx + 1], rW = srho[ly][lx - 1];
-    const CT rN = srho[ly + 1][lx], rS = srho[ly - 1][lx];
-    const CT rNE = srho[ly + 1][lx + 1], rNW = srho[ly + 1][lx - 1];
-    const CT rSE = srho[ly - 1][lx + 1], rSW = srho[ly - 1][lx - 1];
-    const CT gx = c.gxa * (rE - rW) + c.gxb * ((rNE - rNW) + (rSE - rSW));
-    const CT gy = c.gya * (rN - rS) + c.gyb * ((rNE + rNW) - (rSE + rSW));
-
-    if constexpr (ALL) {
-        collide<CT, FORCE, ALL>(c, d, gx, gy);
-    } else {
-        if (c.frame == PRC_FRAME_RAW)
-            collide_raw<CT, FORCE>(c, d, gx, gy);
-        else
-            collide<CT, FORCE, ALL>(c, d, gx, gy);
-    }
+    CT gx, gy;
+    density_gradient(c, srho, g.tx + 1, g.ty + 1, gx, gy);
+    collide_node<CT, FORCE, ALL>(c, d, gx, gy);
 
     const uint32_t o = (uint32_t)y * c.row_bytes + (uint32_t)x * E;
     if (c.nt) {

@@ -1,0 +1,204 @@
+// Two time steps per launch (temporal blocking) for states that live in the
+// last-level cache.
+//
+// A single step per launch makes every node's data cross the cache boundary
+// twice per step, and a launch over a cache-resident grid is one wave of
+// workgroups whose loads, collisions and stores hardly overlap.  Here a
+// workgroup produces its tile two steps ahead from the state three rings
+// further out, keeping the intermediate step in LDS:
+//
+//   region R3 = tile + 3 rings: streamed step-1 populations, step-1 densities
+//   region R2 = tile + 2 rings: step-1 collisions, post-collision state in LDS
+//   region R1 = tile + 1 ring : step-2 streaming out of LDS, step-2 densities
+//   tile                      : step-2 collision, stored to the output state
+//
+// (the density gradient needs the neighbours' densities at the same step, so
+// each step needs one ring more than streaming alone).  Every node passes
+// through exactly the functions of the single-step sweep, in the same order
+// and with the intermediate state rounded to the storage type as a stored
+// state would be, so two steps here give the bits of two single steps.
+//
+// Slots of the rings that fall outside the grid stand in for the node they
+// map to: across a wall the clamped node (the density-gradient reading at
+// walls), across a periodic side the wrapped node.
+#pragma once
+
+#include "prc_collide.hpp"
+#include "prc_device.hpp"
+#include "prc_sweep.hpp"
+
+namespace prc {
+
+// Population a of LDS-resident state: element type of the storage, so that
+// the intermediate step is rounded exactly as a stored state.
+template <typename ST> struct LdsVal;
+template <> struct LdsVal<float> {
+    static __device__ __forceinline__ float put(float x) { return x; }
+    static __device__ __forceinline__ float get(float x) { return x; }
+};
+template <> struct LdsVal<__half> {
+    static __device__ __forceinline__ __half put(float x) { return __float2half_rn(x); }
+    static __device__ __forceinline__ float get(__half x) { return __half2float(x); }
+};
+template <> struct LdsVal<__hip_bfloat16> {
+    static __device__ __forceinline__ __hip_bfloat16 put(float x) { return __float2bfloat16(x); }
+    static __device__ __forceinline__ float get(__hip_bfloat16 x) { return __bfloat162float(x); }
+};
+
+template <int TX, int TY>
+struct Regions2 {
+    static constexpr int T = TX * TY;
+    static constexpr int W3 = TX + 6, H3 = TY + 6, N3 = W3 * H3;
+    static constexpr int W2 = TX + 4, H2 = TY + 4, N2 = W2 * H2;
+    static constexpr int NB = N3 - N2;             // ring 3 alone
+    static constexpr int S2 = (N2 + T - 1) / T;    // R2 slots per thread
+    static constexpr int SB = (NB + T - 1) / T;    // ring-3 slots per thread
+};
+
+// Tile-relative position of ring-3 slot k (top row, bottom row, left column,
+// right column).
+template <int TX, int TY>
+__device__ __forceinline__ void ring3_pos(int k, int &i, int &j)
+{
+    constexpr int W3 = TX + 6, H2 = TY + 4;
+    if (k < W3) { i = k - 3; j = -3; }
+    else if (k < 2 * W3) { i = k - W3 - 3; j = TY + 2; }
+    else if (k < 2 * W3 + H2) { i = -3; j = k - 2 * W3 - 2; }
+    else { i = TX + 2; j = k - 2 * W3 - H2 - 2; }
+}
+
+// Streaming out of the LDS-resident state P (planes [9][H2][W2], tile-relative
+// origin at index (2, 2)) for node (x, y) of the grid whose slot is (hi, hj):
+// the same boundary rules as pull_checked.
+template <typename ST, int BC, int TX, int TY>
+__device__ __forceinline__ void pull_lds(const Coef<typename Mem<ST>::CT> &c,
+                                         const ST (*P)[TY + 4][TX + 4], int x, int y, int hi,
+                                         int hj, typename Mem<ST>::CT d[9])
+{
+    using CT = typename Mem<ST>::CT;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        const int sx = x - EX[a], sy = y - EY[a];
+        bool out = false;
+        if (!Bc<BC>::wrap_x) out |= (sx < 0) | (sx >= c.nx);
+        if (!Bc<BC>::wrap_y) out |= (sy < 0) | (sy >= c.ny);
+        if (!out) {
+            d[a] = LdsVal<ST>::get(P[a][hj - EY[a] + 2][hi - EX[a] + 2]);
+        } else {
+            CT v = LdsVal<ST>::get(P[OPP[a]][hj + 2][hi + 2]);
+            if (Bc<BC>::lid && LIDC[a] != 0 && sy >= c.ny) v += CT(LIDC[a]) * c.lid;
+            d[a] = v;
+        }
+    }
+}
+
+// Node of the grid that slot (i, j) of the tile at (x0, y0) stands for, and
+// the slot whose LDS data that node's streaming reads: across a wall the
+// clamped node and its own slot, across a periodic side the wrapped node and
+// the slot itself (which holds the wrapped node's data).
+template <int BC>
+__device__ __forceinline__ void slot_node(const int nx, const int ny, int x0, int y0, int i,
+                                          int j, int &x, int &y, int &hi, int &hj)
+{
+    x = x0 + i;
+    y = y0 + j;
+    fix_coord<BC>(x, y, nx, ny);
+    hi = Bc<BC>::wrap_x ? i : x - x0;
+    hj = Bc<BC>::wrap_y ? j : y - y0;
+}
+
+// Two steps for the tile of this workgroup: src (state at step n) -> dst
+// (state at step n + 2).  One tile per workgroup, XCD-aware order as k_sweep.
+template <typename ST, int BC, int TX, int TY, bool FORCE, bool ALL>
+__global__ void __launch_bounds__(TX *TY)
+    k_sweep2(const ST *__restrict__ src, ST *__restrict__ dst, const Coef<typename Mem<ST>::CT> c)
+{
+    using CT = typename Mem<ST>::CT;
+    using R = Regions2<TX, TY>;
+    static_assert(sizeof(ST) <= 4, "two-step sweep for FP32 and 16-bit storage");
+    __shared__ CT D1[R::H3][R::W3];        // step-1 densities, origin (3, 3)
+    __shared__ ST P1[9][R::H2][R::W2];     // step-1 post-collision state, origin (2, 2)
+    __shared__ CT D2[TY + 2][TX + 2];      // step-2 densities, origin (1, 1)
+
+    const int tile = (blockIdx.x % kXcds) * c.tiles_per_xcd + blockIdx.x / kXcds;
+    if (tile >= c.tiles_x * c.tiles_y) return;
+    const int x0 = (tile % c.tiles_x) * TX, y0 = (tile / c.tiles_x) * TY;
+    const int t = threadIdx.x;
+    constexpr uint32_t E = sizeof(ST);
+    const rsrc_t rs = make_rsrc(src, c.state_bytes);
+    // every source of every slot of R3 lies inside the grid
+    const bool inner = x0 >= 4 && y0 >= 4 && x0 + TX + 4 <= c.nx && y0 + TY + 4 <= c.ny;
+    auto pull1 = [&](int i, int j, CT d[9]) {
+        if (inner) {
+            pull_inner<ST>(c, rs, (uint32_t)(y0 + j) * c.row_bytes + (uint32_t)(x0 + i - 1) * E, d);
+        } else {
+            int x = x0 + i, y = y0 + j;
+            fix_coord<BC>(x, y, c.nx, c.ny);
+            pull_checked<ST, BC>(c, rs, x, y, d);
+        }
+    };
+
+    // step 1: streaming and densities over R3; R2 populations kept for the
+    // collision
+    CT keep[R::S2][9];
+#pragma unroll
+    for (int s = 0; s < R::S2; ++s) {
+        const int k = t + s * R::T;
+        if (k < R::N2) {
+            const int i = k % R::W2 - 2, j = k / R::W2 - 2;
+            pull1(i, j, keep[s]);
+            D1[j + 3][i + 3] = sum9(keep[s]);
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < R::SB; ++s) {
+        const int k = t + s * R::T;
+        if (k < R::NB) {
+            int i, j;
+            ring3_pos<TX, TY>(k, i, j);
+            CT d[9];
+            pull1(i, j, d);
+            D1[j + 3][i + 3] = sum9(d);
+        }
+    }
+    __syncthreads();
+
+    // step 1: collisions over R2 into LDS
+#pragma unroll
+    for (int s = 0; s < R::S2; ++s) {
+        const int k = t + s * R::T;
+        if (k < R::N2) {
+            const int i = k % R::W2 - 2, j = k / R::W2 - 2;
+            CT gx, gy;
+            density_gradient(c, D1, i + 3, j + 3, gx, gy);
+            collide_node<CT, FORCE, ALL>(c, keep[s], gx, gy);
+#pragma unroll
+            for (int a = 0; a < 9; ++a) P1[a][j + 2][i + 2] = LdsVal<ST>::put(keep[s][a]);
+        }
+    }
+    __syncthreads();
+
+    // step 2: streaming out of LDS over R1 (this thread's tile node, and its
+    // ring node if any), densities
+    const TileGeom<TX, TY> g(t);
+    CT d[9];
+    {
+        int x, y, hi, hj;
+        slot_node<BC>(c.nx, c.ny, x0, y0, g.tx, g.ty, x, y, hi, hj);
+        pull_lds<ST, BC, TX, TY>(c, P1, x, y, hi, hj, d);
+        D2[g.ty + 1][g.tx + 1] = sum9(d);
+    }
+    if (g.ring) {
+        int x, y, hi, hj;
+        slot_node<BC>(c.nx, c.ny, x0, y0, g.hx, g.hy, x, y, hi, hj);
+        CT e[9];
+        pull_lds<ST, BC, TX, TY>(c, P1, x, y, hi, hj, e);
+        D2[g.hy + 1][g.hx + 1] = sum9(e);
+    }
+    __syncthreads();
+
+    // step 2: collision of the tile, stored
+    tile_finish<ST, TX, TY, FORCE, ALL>(c, make_rsrc(dst, c.state_bytes), D2, g, x0, y0, d);
+}
+
+}  // namespace prc

@@ -111,9 +111,13 @@ def test_from_re_rejects_bad_input():
 def test_set_tile_validates_without_gpu():
     p = base()
     capi.prc_set_tile(p, 1)
+    capi.prc_set_tile(p, 7)      # two steps per launch: FP32 and 16-bit storage
     capi.prc_set_tile(p, -1)
     with pytest.raises(capi.PrcError):
-        capi.prc_set_tile(p, 7)
+        capi.prc_set_tile(p, 9)
+    p.storage = capi.PRC_F64
+    with pytest.raises(capi.PrcError):
+        capi.prc_set_tile(p, 5)
 
 
 # ---- batches: host-side argument checks (nothing is launched) -------------
@@ -231,3 +235,11 @@ def test_step_rejects_bad_buffers_before_launching(a, b, n):
     with pytest.raises(capi.PrcError) as e:
         capi.prc_step(base(), a, b, n)
     assert e.value.status == capi.PRC_EINVAL
+
+
+def test_tile_info():
+    shapes = [capi.prc_tile_info(t) for t in range(9)]
+    assert shapes[0] == (64, 4, 1) and shapes[8] == (32, 32, 2)
+    assert [s[2] for s in shapes] == [1] * 5 + [2] * 4
+    with pytest.raises(capi.PrcError):
+        capi.prc_tile_info(9)

@@ -276,7 +276,7 @@ def test_tune_returns_a_shape_and_results_are_unchanged(torch_cuda):
     a = make_solver(s)
     a.step(6)
     t = capi.prc_tune(a.p)
-    assert t in range(5)
+    assert t in range(9)
     b = make_solver(s)
     b.step(6)
     capi.prc_set_tile(a.p, -1)
