@@ -286,14 +286,15 @@ prc_status prc_batch_solve(prc_batch *b, double tol, int64_t check_every, int64_
                            int32_t *status, int64_t *steps, double *hist, int64_t hist_cap,
                            int64_t *hist_len, hipStream_t stream);
 
-/* Autotuner for the batch sweep: time each tile shape (indices as for
- * prc_tune) on the current members, sweeping f_a into f_b (f_a, which holds
+/* Autotuner for the batch sweep: time each tile shape a batch can use
+ * (indices 0 .. 6 of prc_tune: the single-step shapes and the two-step 64 x 8
+ * and 32 x 16; no two-step shape for FP64) on the current members, sweeping f_a into f_b (f_a, which holds
  * the state, is only read), and keep the fastest for this batch.  tile_out
  * (may be NULL) receives it.  Synchronises the stream. */
 prc_status prc_batch_tune(prc_batch *b, int32_t *tile_out, hipStream_t stream);
 
-/* Use tile shape `tile` (0 .. 4, as for prc_tune) for this batch's sweeps.
- * Host only. */
+/* Use tile shape `tile` (0 .. 6, as for prc_batch_tune) for this batch's
+ * sweeps.  Host only. */
 prc_status prc_batch_set_tile(prc_batch *b, int32_t tile);
 
 /* ---- Serving: steady-state solve requests with continuous batching -----
@@ -334,7 +335,8 @@ typedef struct {
                              and a velocity snapshot (16 B/node) each */
     int32_t max_active;   /* at most this many requests in the batch; 0 = no
                              limit, 1 = one at a time */
-    int32_t tile;         /* sweep tile shape (0 .. 4), -1 for the default */
+    int32_t tile;         /* sweep tile shape (0 .. 6, as for prc_batch_tune),
+                             -1 for the default */
 } prc_serve_config;
 
 /* Serve requests reqs[0 .. n) (host array, arrivals non-decreasing) and write

@@ -24,6 +24,7 @@
 #include "prc_host.hpp"
 #include "prc_reduce.hpp"
 #include "prc_sweep.hpp"
+#include "prc_sweep2.hpp"
 
 namespace prc {
 
@@ -127,7 +128,10 @@ namespace prc {
 static int batch_tile(const prc_batch &b)
 {
     if (b.tile >= 0) return b.tile;
-    return 0;  // 64 x 4: the members of a batch are mostly narrow grids
+    // measured on MI355X for batches of 64..512-wide cavities: 32 x 16 tiles
+    // waste few threads at ragged edges, and two steps per launch halve the
+    // state traffic (no two-step shape for FP64)
+    return b.storage == PRC_F64 ? 4 : 6;
 }
 
 static void drop_graph(prc_batch &b)
@@ -215,48 +219,86 @@ static prc_status ensure_tables(prc_batch &b, hipStream_t s)
     return PRC_DISPATCH(q, build_tables, b, s);
 }
 
-template <typename ST, int BC, int TX, int TY, bool FORCE, bool ALL>
+template <typename ST, int BC, int TX, int TY, bool FORCE, bool ALL, int STEPS>
 static prc_status launch_batch_shape(const prc_batch &b, int v, int parity, hipStream_t s)
 {
     using CT = typename Mem<ST>::CT;
     const int nt = b.ntiles[v];
     const int per_xcd = (nt + kXcds - 1) / kXcds;
-    hipLaunchKernelGGL((k_sweep_batch<ST, BC, TX, TY, FORCE, ALL>), dim3(per_xcd * kXcds),
-                       dim3(TX * TY), 0, s, (const BatchTile *)b.d_tiles[v].ptr, nt, per_xcd,
-                       (const BatchMember<CT> *)b.d_members.ptr, parity);
+    if constexpr (STEPS == 2) {
+        if constexpr (sizeof(ST) <= 4)
+            hipLaunchKernelGGL((k_sweep_batch2<ST, BC, TX, TY, FORCE, ALL>),
+                               dim3(per_xcd * kXcds), dim3(TX * TY), 0, s,
+                               (const BatchTile *)b.d_tiles[v].ptr, nt, per_xcd,
+                               (const BatchMember<CT> *)b.d_members.ptr, parity);
+        else
+            return fail(PRC_EINVAL, "two-step sweep shapes need FP32 or 16-bit storage");
+    } else {
+        hipLaunchKernelGGL((k_sweep_batch<ST, BC, TX, TY, FORCE, ALL>), dim3(per_xcd * kXcds),
+                           dim3(TX * TY), 0, s, (const BatchTile *)b.d_tiles[v].ptr, nt, per_xcd,
+                           (const BatchMember<CT> *)b.d_members.ptr, parity);
+    }
     HIP_TRY(hipGetLastError());
     return PRC_OK;
 }
 
-template <typename ST, int BC, int TX, int TY>
+template <typename ST, int BC, int TX, int TY, int STEPS>
 static prc_status launch_batch_variants(const prc_batch &b, int parity, hipStream_t s)
 {
     prc_status st = PRC_OK;
-    if (b.ntiles[0] > 0) st = launch_batch_shape<ST, BC, TX, TY, false, true>(b, 0, parity, s);
+    if (b.ntiles[0] > 0)
+        st = launch_batch_shape<ST, BC, TX, TY, false, true, STEPS>(b, 0, parity, s);
     if (st == PRC_OK && b.ntiles[1] > 0)
-        st = launch_batch_shape<ST, BC, TX, TY, true, false>(b, 1, parity, s);
+        st = launch_batch_shape<ST, BC, TX, TY, true, false, STEPS>(b, 1, parity, s);
     return st;
 }
 
-// one sweep of every active member (reads buf[parity], writes the other)
+// One launch over every active member, reading buf[parity] and writing the
+// other: two steps if `two` (the batch's shape must be a two-step one), else
+// one step with the batch's shape or its single-step twin.
 template <typename ST, int BC>
-static prc_status launch_batch_sweep(const prc_batch &b, int parity, hipStream_t s)
+static prc_status launch_batch_sweep(const prc_batch &b, int parity, bool two, hipStream_t s)
 {
     switch (batch_tile(b)) {
-    case 1: return launch_batch_variants<ST, BC, 64, 8>(b, parity, s);
-    case 2: return launch_batch_variants<ST, BC, 128, 4>(b, parity, s);
-    case 3: return launch_batch_variants<ST, BC, 32, 8>(b, parity, s);
-    case 4: return launch_batch_variants<ST, BC, 32, 16>(b, parity, s);
-    default: return launch_batch_variants<ST, BC, 64, 4>(b, parity, s);
+    case 1: return launch_batch_variants<ST, BC, 64, 8, 1>(b, parity, s);
+    case 2: return launch_batch_variants<ST, BC, 128, 4, 1>(b, parity, s);
+    case 3: return launch_batch_variants<ST, BC, 32, 8, 1>(b, parity, s);
+    case 4: return launch_batch_variants<ST, BC, 32, 16, 1>(b, parity, s);
+    case 5:
+        return two ? launch_batch_variants<ST, BC, 64, 8, 2>(b, parity, s)
+                   : launch_batch_variants<ST, BC, 64, 8, 1>(b, parity, s);
+    case 6:
+        return two ? launch_batch_variants<ST, BC, 32, 16, 2>(b, parity, s)
+                   : launch_batch_variants<ST, BC, 32, 16, 1>(b, parity, s);
+    default: return launch_batch_variants<ST, BC, 64, 4, 1>(b, parity, s);
     }
 }
 
-static prc_status batch_sweep(const prc_batch &b, int parity, hipStream_t s)
+static prc_status batch_sweep(const prc_batch &b, int parity, hipStream_t s, bool two = false)
 {
     prc_params q{};
     q.storage = b.storage;
     q.bc = b.bc;
-    return PRC_DISPATCH(q, launch_batch_sweep, b, parity, s);
+    return PRC_DISPATCH(q, launch_batch_sweep, b, parity, two, s);
+}
+
+// Steps [k0, k0 + n) of every active member (step k reads buf[k & 1]); with a
+// two-step shape, pairs of two-step launches cover the steps in fours from an
+// even step (as for single problems), single steps the rest.
+static prc_status batch_run(const prc_batch &b, int64_t k0, int64_t n, hipStream_t s)
+{
+    prc_status st = PRC_OK;
+    int64_t k = k0;
+    const int64_t end = k0 + n;
+    if (kTiles[batch_tile(b)].steps == 2) {
+        if (k < end && (k & 1)) st = batch_sweep(b, (int)(k++ & 1), s);
+        for (; k + 4 <= end && st == PRC_OK; k += 4) {
+            st = batch_sweep(b, 0, s, true);
+            if (st == PRC_OK) st = batch_sweep(b, 1, s, true);
+        }
+    }
+    for (; k < end && st == PRC_OK; ++k) st = batch_sweep(b, (int)(k & 1), s);
+    return st;
 }
 
 static prc_status capture_graph(prc_batch &b, int nsteps)
@@ -267,7 +309,7 @@ static prc_status capture_graph(prc_batch &b, int nsteps)
     prc_status st = PRC_OK;
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        for (int k = 0; k < nsteps && st == PRC_OK; ++k) st = batch_sweep(b, k & 1, cs);
+        st = batch_run(b, 0, nsteps, cs);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(cs, &g);
         if (e == hipSuccess && st == PRC_OK) {
@@ -307,9 +349,7 @@ static prc_status batch_steps(prc_batch &b, int64_t nsteps, hipStream_t s)
             if ((st = capture_graph(b, gsteps)) != PRC_OK) return st;
         for (; k + gsteps <= nsteps; k += gsteps) HIP_TRY(hipGraphLaunch(b.gexec, s));
     }
-    for (; k < nsteps; ++k)
-        if ((st = batch_sweep(b, (int)(k & 1), s)) != PRC_OK) return st;
-    return PRC_OK;
+    return batch_run(b, k, nsteps - k, s);
 }
 
 template <typename ST, int BC>
@@ -586,7 +626,8 @@ prc_status prc_batch_tune(prc_batch *b, int32_t *tile_out, hipStream_t stream)
     float best_ms = 0.0f;
     hipError_t he = hipEventCreate(&e0);
     if (he == hipSuccess) he = hipEventCreate(&e1);
-    for (int t = 0; t < kNumSingleStepTiles && he == hipSuccess && st == PRC_OK; ++t) {
+    for (int t = 0; t < kNumBatchTiles && he == hipSuccess && st == PRC_OK; ++t) {
+        if (kTiles[t].steps == 2 && b->storage == PRC_F64) continue;
         b->tile = t;
         b->dirty = true;
         if ((st = ensure_tables(*b, stream)) != PRC_OK) break;
@@ -594,13 +635,14 @@ prc_status prc_batch_tune(prc_batch *b, int32_t *tile_out, hipStream_t stream)
         // always f_a -> f_b: the state in f_a is only read
         for (int k = 0; k < kWarm + kTimed && st == PRC_OK && he == hipSuccess; ++k) {
             if (k == kWarm) he = hipEventRecord(e0, stream);
-            st = batch_sweep(*b, 0, stream);
+            st = batch_sweep(*b, 0, stream, kTiles[t].steps == 2);
         }
         if (st != PRC_OK || he != hipSuccess) break;
         he = hipEventRecord(e1, stream);
         if (he == hipSuccess) he = hipEventSynchronize(e1);
         float ms = 0.0f;
         if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        ms /= (float)kTiles[t].steps;  // per time step
         if (he == hipSuccess && (best < 0 || ms < best_ms)) {
             best = t;
             best_ms = ms;
@@ -620,9 +662,11 @@ prc_status prc_batch_set_tile(prc_batch *b, int32_t tile)
 {
     prc_status st = batch_ok(b);
     if (st != PRC_OK) return st;
-    if (tile < 0 || tile >= kNumSingleStepTiles)
+    if (tile < 0 || tile >= kNumBatchTiles)
         return fail(PRC_EINVAL, "tile %d out of range for a batch (0 .. %d)", tile,
-                    kNumSingleStepTiles - 1);
+                    kNumBatchTiles - 1);
+    if (kTiles[tile].steps == 2 && b->storage == PRC_F64)
+        return fail(PRC_EINVAL, "tile %d (two steps per launch) needs FP32 or 16-bit storage", tile);
     if (tile != b->tile) {
         b->tile = tile;
         b->dirty = true;

@@ -183,6 +183,10 @@ constexpr TileShape kTiles[] = {{64, 4, 1},  {64, 8, 1},  {128, 4, 1}, {32, 8, 1
                                 {64, 8, 2},  {32, 16, 2}, {64, 16, 2}, {32, 32, 2}};
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 constexpr int kNumSingleStepTiles = 5;  // indices below this advance one step
+// Batches use the shapes below this index: the single-step ones and the
+// two-step shapes whose single-step twin has the same tile (64 x 8 -> 1,
+// 32 x 16 -> 4), so that one tile list serves both.
+constexpr int kNumBatchTiles = 7;
 
 // Whether tile shape `tile` may run problem p (two-step shapes: no FP64).
 inline bool tile_allowed(const prc_params &p, int tile)

@@ -198,7 +198,8 @@ extern "C" prc_status prc_serve(const prc_serve_config *cfg, const prc_request *
     if (cfg->max_steps < 0 || cfg->max_steps % cfg->check_every)
         return fail(PRC_EINVAL, "max_steps must be a non-negative multiple of check_every");
     if (!(cfg->tol >= 0.0)) return fail(PRC_EINVAL, "tol must be >= 0");
-    if (cfg->tile < -1 || cfg->tile >= kNumSingleStepTiles)
+    if (cfg->tile < -1 || cfg->tile >= kNumBatchTiles ||
+        (cfg->tile >= 0 && kTiles[cfg->tile].steps == 2 && cfg->storage == PRC_F64))
         return fail(PRC_EINVAL, "tile out of range");
     if (cfg->hbm_budget < 4096) return fail(PRC_EINVAL, "hbm_budget too small");
     for (int32_t i = 1; i < n; ++i)

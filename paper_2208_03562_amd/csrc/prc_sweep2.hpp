@@ -107,11 +107,11 @@ __device__ __forceinline__ void slot_node(const int nx, const int ny, int x0, in
     hj = Bc<BC>::wrap_y ? j : y - y0;
 }
 
-// Two steps for the tile of this workgroup: src (state at step n) -> dst
-// (state at step n + 2).  One tile per workgroup, XCD-aware order as k_sweep.
+// Two steps for the tile at (x0, y0) of one problem: src (state at step n) ->
+// dst (state at step n + 2).  Called by the whole workgroup.
 template <typename ST, int BC, int TX, int TY, bool FORCE, bool ALL>
-__global__ void __launch_bounds__(TX *TY)
-    k_sweep2(const ST *__restrict__ src, ST *__restrict__ dst, const Coef<typename Mem<ST>::CT> c)
+__device__ __forceinline__ void sweep2_tile(const Coef<typename Mem<ST>::CT> &c,
+                                            const void *src, void *dst, int x0, int y0)
 {
     using CT = typename Mem<ST>::CT;
     using R = Regions2<TX, TY>;
@@ -120,9 +120,6 @@ __global__ void __launch_bounds__(TX *TY)
     __shared__ ST P1[9][R::H2][R::W2];     // step-1 post-collision state, origin (2, 2)
     __shared__ CT D2[TY + 2][TX + 2];      // step-2 densities, origin (1, 1)
 
-    const int tile = (blockIdx.x % kXcds) * c.tiles_per_xcd + blockIdx.x / kXcds;
-    if (tile >= c.tiles_x * c.tiles_y) return;
-    const int x0 = (tile % c.tiles_x) * TX, y0 = (tile / c.tiles_x) * TY;
     const int t = threadIdx.x;
     constexpr uint32_t E = sizeof(ST);
     const rsrc_t rs = make_rsrc(src, c.state_bytes);
@@ -199,6 +196,32 @@ __global__ void __launch_bounds__(TX *TY)
 
     // step 2: collision of the tile, stored
     tile_finish<ST, TX, TY, FORCE, ALL>(c, make_rsrc(dst, c.state_bytes), D2, g, x0, y0, d);
+}
+
+// One problem, one tile per workgroup, XCD-aware order as k_sweep.
+template <typename ST, int BC, int TX, int TY, bool FORCE, bool ALL>
+__global__ void __launch_bounds__(TX *TY)
+    k_sweep2(const ST *__restrict__ src, ST *__restrict__ dst, const Coef<typename Mem<ST>::CT> c)
+{
+    const int tile = (blockIdx.x % kXcds) * c.tiles_per_xcd + blockIdx.x / kXcds;
+    if (tile >= c.tiles_x * c.tiles_y) return;
+    const int x0 = (tile % c.tiles_x) * TX, y0 = (tile / c.tiles_x) * TY;
+    sweep2_tile<ST, BC, TX, TY, FORCE, ALL>(c, src, dst, x0, y0);
+}
+
+// A tile list over many problems (batches), as k_sweep_batch: two steps from
+// buf[parity] into buf[parity ^ 1].
+template <typename ST, int BC, int TX, int TY, bool FORCE, bool ALL>
+__global__ void __launch_bounds__(TX *TY)
+    k_sweep_batch2(const BatchTile *__restrict__ tiles, int ntiles, int tiles_per_xcd,
+                   const BatchMember<typename Mem<ST>::CT> *__restrict__ members, int parity)
+{
+    const int t = (blockIdx.x % kXcds) * tiles_per_xcd + blockIdx.x / kXcds;
+    if (t >= ntiles) return;
+    const BatchTile tl = tiles[t];
+    const BatchMember<typename Mem<ST>::CT> &m = members[tl.member];
+    sweep2_tile<ST, BC, TX, TY, FORCE, ALL>(m.c, m.buf[parity], const_cast<void *>(m.buf[parity ^ 1]),
+                                            tl.x0, tl.y0);
 }
 
 }  // namespace prc

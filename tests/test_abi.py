@@ -159,10 +159,11 @@ def test_batch_host_checks():
             capi.prc_batch_solve(b, 1e-6, 100, 250)   # max_steps not a multiple
         with pytest.raises(capi.PrcError):
             capi.prc_batch_solve(b, 1e-6, 101, 202)   # odd check interval
-        for t in (-1, 5):
+        for t in (-1, 7):
             with pytest.raises(capi.PrcError):
                 capi.prc_batch_set_tile(b, t)
         capi.prc_batch_set_tile(b, 2)
+        capi.prc_batch_set_tile(b, 6)      # two steps per launch
     finally:
         capi.prc_batch_destroy(b)
 
@@ -183,7 +184,7 @@ def serve_cfg(**kw):
 
 
 @pytest.mark.parametrize("kw", [dict(check_every=99), dict(check_every=0), dict(max_steps=150),
-                                dict(tol=-1.0), dict(tile=5), dict(hbm_budget=100),
+                                dict(tol=-1.0), dict(tile=7), dict(hbm_budget=100),
                                 dict(storage=7), dict(bc=4)])
 def test_serve_rejects_bad_config(kw):
     with pytest.raises(capi.PrcError) as e:
@@ -243,3 +244,13 @@ def test_tile_info():
     assert [s[2] for s in shapes] == [1] * 5 + [2] * 4
     with pytest.raises(capi.PrcError):
         capi.prc_tile_info(9)
+
+
+def test_batch_two_step_shapes_refused_for_fp64():
+    b = capi.prc_batch_create(capi.PRC_F64, capi.PRC_BC_CAVITY)
+    try:
+        with pytest.raises(capi.PrcError):
+            capi.prc_batch_set_tile(b, 5)
+        capi.prc_batch_set_tile(b, 4)
+    finally:
+        capi.prc_batch_destroy(b)

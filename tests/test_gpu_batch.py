@@ -44,7 +44,7 @@ def alone(s, tol, K, max_steps):
     return sol, st, n, hist
 
 
-@pytest.mark.parametrize("tile", [None, 1, 2])
+@pytest.mark.parametrize("tile", [None, 1, 2, 5, 6])
 def test_batch_solve_is_bitwise_the_single_solve(torch_cuda, tile):
     from paper_2208_03562_amd import solver
     tol, K, max_steps = 1e-4, 100, 1600
@@ -109,12 +109,15 @@ def test_member_joining_later_and_removal(torch_cuda):
     b.close()
 
 
-@pytest.mark.parametrize("storage", ["f64", "f16", "bf16"])
-def test_batch_other_storage_types(torch_cuda, storage):
+@pytest.mark.parametrize("storage,tile", [("f64", None), ("f16", None), ("bf16", None),
+                                          ("f16", 5), ("bf16", 6)])
+def test_batch_other_storage_types(torch_cuda, storage, tile):
     from paper_2208_03562_amd import capi, solver
     specs = [dict(MIX[0], storage=storage), dict(MIX[1], storage=storage),
              dict(MIX[6], storage=storage)]
     b = solver.Batch(storage=getattr(capi, "PRC_" + storage.upper()))
+    if tile is not None:
+        b.set_tile(tile)
     for s in specs:
         b.add(lib_params(s))
     status, steps, hists = b.solve(1e-3, 50, 400, hist_cap=8)
@@ -155,7 +158,7 @@ def test_batch_tune_keeps_results(torch_cuda):
         c.add(lib_params(s))
     a.step(20)
     t = a.tune()          # sweeps f_a into f_b only: the state is unchanged
-    assert t in range(5)
+    assert t in range(7)
     a.step(40)
     c.step(60)
     for i in range(5):
