@@ -390,7 +390,7 @@ def main():
                     help="print per-grid kernel durations of a kernel-trace run in this folder")
     ap.add_argument("--batch-instances", type=int, default=256,
                     help="instances of the batched-solve workload (0: skip)")
-    ap.add_argument("--serve-requests", type=int, default=200,
+    ap.add_argument("--serve-requests", type=int, default=500,
                     help="requests of the serving trace (0: skip)")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20000)

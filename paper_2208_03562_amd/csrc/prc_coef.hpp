@@ -41,6 +41,7 @@ struct Coef {
     CT ig1;                 // 1/gamma - 1
     CT Pg, Qg;              // 4/gamma^2 - 1/gamma, 1/gamma^2 - 1/gamma
     CT g3;                  // 1/gamma^2 - 3/gamma + 2 (third-order equilibria, eq. 14)
+    CT g3p1, g34p1;         // g3 + 1, 4 g3 + 1 (raw moments after the collision)
     CT Ab, Bb;              // (U_gamma c2 - 1)/2, (U_gamma c2 - r^2)/2 (eq. 43)
     CT a1, a2;              // 3 c2 - 1, 3 c2 - r^2 (anisotropy factors)
     CT cb0, cs0;            // -2 c2 / omega_xi, 2 c2 / omega_nu (eq. 46)
@@ -97,6 +98,8 @@ inline Coef<CT> make_coef(const prc_params &p, int64_t row_stride, int64_t plane
     c.Pg = CT(4.0 / (g * g) - 1.0 / g);
     c.Qg = CT(Qg);
     c.g3 = CT(1.0 / (g * g) - 3.0 / g + 2.0);
+    c.g3p1 = CT(1.0 / (g * g) - 3.0 / g + 3.0);
+    c.g34p1 = CT(4.0 / (g * g) - 12.0 / g + 9.0);
     c.Ab = CT(0.5 * (Ug * c2 - 1.0));
     c.Bb = CT(0.5 * (Ug * c2 - r * r));
     c.a1 = CT(3.0 * c2 - 1.0);

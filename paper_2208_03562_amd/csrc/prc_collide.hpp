@@ -221,6 +221,103 @@ __device__ __forceinline__ void collide(const Coef<CT> &c, CT d[9], CT gx, CT gy
     for (int a = 0; a < 9; ++a) d[a] = q[QJ[a]][QI[a]];
 }
 
+// The method as the paper runs it (every correction, unit rates for the
+// non-hydrodynamic moments, no body force), written for few operations.
+// With omega_xi = omega_3 = omega_4 = 1 the post-collision k2s, k21, k12 and
+// k22 are their (corrected) equilibria, so the third- and fourth-order moments
+// of f are never needed: only rho, j and the raw second moments are formed,
+// and the second central moments follow from k20 = m20 - rho ux^2,
+// k02 = m02 - rho uy^2, k11 = m11 - rho ux uy.  After the collision the first
+// central moments are zero and j is unchanged, so the binomial shift back to
+// raw moments has closed forms; the raw moments of the deviations (those of
+// f minus rho0 (1,0,c2)x(1,0,c2)) then give the new deviations through
+// P^-1 S^-1.
+template <typename CT>
+__device__ __forceinline__ void collide_plain(const Coef<CT> &c, CT d[9], CT gx, CT gy)
+{
+    CT q[3][3];  // [e_y + 1][e_x + 1]
+#pragma unroll
+    for (int a = 0; a < 9; ++a) q[QJ[a]][QI[a]] = d[a];
+    CT X0[3], X1[3], X2[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        X1[j] = q[j][2] - q[j][0];
+        X2[j] = q[j][2] + q[j][0];
+        X0[j] = X2[j] + q[j][1];
+    }
+    const CT drho = (X0[0] + X0[1]) + X0[2];
+    const CT rho = c.rho0 + drho;
+    const CT irho = recip(rho);
+    const CT jx = (X1[0] + X1[1]) + X1[2], jy = c.r * (X0[2] - X0[0]);
+    const CT ux = jx * irho, uy = jy * irho;
+    const CT ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
+    const CT u2s = ux2 + uy2;
+
+    // raw second moments of the deviations, then the central ones of f
+    // minus rho0 c2 (k20, k02) and k11
+    const CT m20 = (X2[0] + X2[1]) + X2[2];
+    const CT m02 = c.r2 * (X0[2] + X0[0]);
+    const CT m11 = c.r * (X1[2] - X1[0]);
+    const CT k20 = m20 - ux * jx;
+    const CT k02 = m02 - uy * jy;
+    const CT k11 = m11 - uy * jx;
+    const CT k2s = k20 + k02;  // minus 2 c2 rho0
+    const CT k2d = k20 - k02;
+
+    // preconditioned equilibria (eq. 14), minus the same constants
+    const CT irh = c.ig1 * rho;
+    const CT e2s = c.c2x2 * drho + irh * u2s;
+    const CT e2d = irh * (ux2 - uy2);
+    const CT e11 = irh * uxy;
+
+    CT cor2s, cor2d, cor11;
+    corrections<CT, true>(c, ux, uy, ux2, uy2, uxy, k2s - e2s, k2d - e2d, gx, gy, cor2s, cor2d,
+                          cor11);
+
+    // post-collision second central moments (omega_xi = 1: k2s takes its
+    // equilibrium), k20 and k02 minus rho0 c2
+    const CT K2s = e2s + cor2s;
+    const CT K2d = k2d + c.om_nu * ((e2d + cor2d) - k2d);
+    const CT K11 = k11 + c.om_nu * ((e11 + cor11) - k11);
+    const CT K20 = CT(0.5) * (K2s + K2d), K02 = CT(0.5) * (K2s - K2d);
+
+    // raw moments of the new deviations from the central ones (first central
+    // moments zero, k21 = g3 rho ux^2 uy, k12 = g3 rho ux uy^2, k22 = c2^2 rho):
+    // m10, m01 are jx, jy as before the collision
+    const CT w20 = K20 + ux * jx;
+    const CT w02 = K02 + uy * jy;
+    const CT w11 = K11 + uy * jx;
+    const CT A = K20 + c.c2rho0, B = K02 + c.c2rho0;  // k20, k02 of f
+    const CT rg = c.g3p1 * rho;                      // (g3 + 1) rho
+    const CT w21 = uy * (rg * ux2 + A) + (ux + ux) * K11;
+    const CT w12 = ux * (rg * uy2 + B) + (uy + uy) * K11;
+    const CT w22 = ((c.c2sq * drho + (c.g34p1 * rho) * (ux2 * uy2)) + (ux2 * B + uy2 * A)) +
+                   CT(4) * uxy * K11;
+
+    // y-transform back for each x-moment, halved (the halves of the
+    // x-transform folded in) ...
+    CT G[3][3];  // [x-moment][e_y + 1]
+    auto yinv = [&](CT K0, CT K1, CT K2, CT *g) {
+        const CT a = c.qinv_r * K1, b = c.qinv_r2 * K2;  // 1/(4r), 1/(4r^2)
+        g[0] = b - a;
+        g[1] = CT(0.5) * K0 - CT(2) * b;
+        g[2] = b + a;
+    };
+    yinv(drho, jy, w02, G[0]);
+    yinv(jx, w11, w12, G[1]);
+    yinv(w20, w21, w22, G[2]);
+    // ... then the x-transform back for each row
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const CT K0 = G[0][j], K1 = G[1][j], K2 = G[2][j];
+        q[j][0] = K2 - K1;
+        q[j][1] = CT(2) * (K0 - K2);
+        q[j][2] = K2 + K1;
+    }
+#pragma unroll
+    for (int a = 0; a < 9; ++a) d[a] = q[QJ[a]][QI[a]];
+}
+
 // Raw-moment (rest-frame) collision, PRNR-LBM.  Deviations and incremental
 // form as in collide(); the raw moments of rho0 w are exactly the constant
 // tensor rho0 (1,0,c2)x(1,0,c2), so the raw moments of the deviations are

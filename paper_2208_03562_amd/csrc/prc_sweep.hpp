@@ -84,12 +84,14 @@ __device__ __forceinline__ void density_gradient(const Coef<CT> &c, const CT (*D
     gy = c.gya * (rN - rS) + c.gyb * ((rNE + rNW) - (rSE + rSW));
 }
 
-// The collision of one node: the specialised central-moment update, or in
-// the general instance the frame read at run time.
+// The collision of one node: the specialised update of the method as the
+// paper runs it, or in the general instance the frame read at run time.
 template <typename CT, bool FORCE, bool ALL>
 __device__ __forceinline__ void collide_node(const Coef<CT> &c, CT d[9], CT gx, CT gy)
 {
-    if constexpr (ALL) {
+    if constexpr (ALL && !FORCE) {
+        collide_plain<CT>(c, d, gx, gy);
+    } else if constexpr (ALL) {
         collide<CT, FORCE, ALL>(c, d, gx, gy);
     } else {
         if (c.frame == PRC_FRAME_RAW)

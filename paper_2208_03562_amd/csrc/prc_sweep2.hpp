@@ -92,6 +92,15 @@ __device__ __forceinline__ void pull_lds(const Coef<typename Mem<ST>::CT> &c,
     }
 }
 
+// The same for a slot whose sources all lie inside the grid.
+template <typename ST, int TX, int TY>
+__device__ __forceinline__ void pull_lds_inner(const ST (*P)[TY + 4][TX + 4], int hi, int hj,
+                                               typename Mem<ST>::CT d[9])
+{
+#pragma unroll
+    for (int a = 0; a < 9; ++a) d[a] = LdsVal<ST>::get(P[a][hj - EY[a] + 2][hi - EX[a] + 2]);
+}
+
 // Node of the grid that slot (i, j) of the tile at (x0, y0) stands for, and
 // the slot whose LDS data that node's streaming reads: across a wall the
 // clamped node and its own slot, across a periodic side the wrapped node and
@@ -179,18 +188,30 @@ __device__ __forceinline__ void sweep2_tile(const Coef<typename Mem<ST>::CT> &c,
     // ring node if any), densities
     const TileGeom<TX, TY> g(t);
     CT d[9];
-    {
-        int x, y, hi, hj;
-        slot_node<BC>(c.nx, c.ny, x0, y0, g.tx, g.ty, x, y, hi, hj);
-        pull_lds<ST, BC, TX, TY>(c, P1, x, y, hi, hj, d);
+    // every source of every slot of R1 lies inside the grid
+    const bool inner2 = x0 >= 2 && y0 >= 2 && x0 + TX + 2 <= c.nx && y0 + TY + 2 <= c.ny;
+    if (inner2) {
+        pull_lds_inner<ST, TX, TY>(P1, g.tx, g.ty, d);
         D2[g.ty + 1][g.tx + 1] = sum9(d);
-    }
-    if (g.ring) {
-        int x, y, hi, hj;
-        slot_node<BC>(c.nx, c.ny, x0, y0, g.hx, g.hy, x, y, hi, hj);
-        CT e[9];
-        pull_lds<ST, BC, TX, TY>(c, P1, x, y, hi, hj, e);
-        D2[g.hy + 1][g.hx + 1] = sum9(e);
+        if (g.ring) {
+            CT e[9];
+            pull_lds_inner<ST, TX, TY>(P1, g.hx, g.hy, e);
+            D2[g.hy + 1][g.hx + 1] = sum9(e);
+        }
+    } else {
+        {
+            int x, y, hi, hj;
+            slot_node<BC>(c.nx, c.ny, x0, y0, g.tx, g.ty, x, y, hi, hj);
+            pull_lds<ST, BC, TX, TY>(c, P1, x, y, hi, hj, d);
+            D2[g.ty + 1][g.tx + 1] = sum9(d);
+        }
+        if (g.ring) {
+            int x, y, hi, hj;
+            slot_node<BC>(c.nx, c.ny, x0, y0, g.hx, g.hy, x, y, hi, hj);
+            CT e[9];
+            pull_lds<ST, BC, TX, TY>(c, P1, x, y, hi, hj, e);
+            D2[g.hy + 1][g.hx + 1] = sum9(e);
+        }
     }
     __syncthreads();
 
