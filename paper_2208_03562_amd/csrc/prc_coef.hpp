@@ -48,6 +48,9 @@ struct Coef {
     CT mhxi, mhnu;          // -(1/omega_xi - 1/2), -(1/omega_nu - 1/2)
     CT mhxi2, mhnu2;        // twice those (density-gradient terms)
     CT kq11, kl11;          // k11 corrections: -Q_gamma h_nu, -(1/gamma - 1) h_nu c2
+    CT hPg, hQg;            // P_gamma / 2, Q_gamma / 2
+    CT cbx0, cby0, csx0, csy0;  // a1/2 + cb0, a2/2 + cb0, a1/2 - cs0, cs0 - a2/2
+    CT c4hnu;               // 4 c2 h_nu
     CT om_nu, om_xi, om_3, om_4;
     CT fxh, fyh;            // F / (2 gamma) (eq. hydrodynamicfields)
     CT fxg, fyg;            // F / gamma: change of the first-order central moments
@@ -112,6 +115,13 @@ inline Coef<CT> make_coef(const prc_params &p, int64_t row_stride, int64_t plane
     c.mhnu2 = CT(-2.0 * hnu);
     c.kq11 = CT(-Qg * hnu);
     c.kl11 = CT(-(1.0 / g - 1.0) * hnu * c2);
+    c.hPg = CT(0.5 * (4.0 / (g * g) - 1.0 / g));
+    c.hQg = CT(0.5 * Qg);
+    c.cbx0 = CT(0.5 * (3.0 * c2 - 1.0) - 2.0 * c2 / p.omega_xi);
+    c.cby0 = CT(0.5 * (3.0 * c2 - r * r) - 2.0 * c2 / p.omega_xi);
+    c.csx0 = CT(0.5 * (3.0 * c2 - 1.0) - 2.0 * c2 / p.omega_nu);
+    c.csy0 = CT(2.0 * c2 / p.omega_nu - 0.5 * (3.0 * c2 - r * r));
+    c.c4hnu = CT(4.0 * c2 * hnu);
     c.om_nu = CT(p.omega_nu);
     c.om_xi = CT(p.omega_xi);
     c.om_3 = CT(p.omega_3);

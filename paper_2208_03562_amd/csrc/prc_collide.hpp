@@ -221,17 +221,51 @@ __device__ __forceinline__ void collide(const Coef<CT> &c, CT d[9], CT gx, CT gy
     for (int a = 0; a < 9; ++a) d[a] = q[QJ[a]][QI[a]];
 }
 
+// Changes of k2s, k2d and k11 in the collision of the method as the paper
+// runs it (omega_xi = 1), from the non-equilibrium parts n2s, n2d, n11.  The
+// strain rates solve the two equations of eq. 46, cbx Dx + cby Dy = R2s and
+// csx Dx + csy Dy = R2d (D = rho times the strain rate); with them the
+// theta and lambda terms of eq. 38-39 sum to
+//   k2s: -(n2s + 2 c2 (Dx + Dy))          (omega_xi = 1)
+//   k2d: -2 h_nu (n2d + (2 c2 / omega_nu) (Dx - Dy)),
+// so that relaxing with omega_xi = 1 and omega_nu gives the changes
+//   d2s = -2 n2s - 2 c2 (Dx + Dy),  d2d = -2 n2d - 4 c2 h_nu (Dx - Dy)
+// (the same terms as in corrections(), summed in closed form).
+template <typename CT>
+__device__ __forceinline__ void increments_plain(const Coef<CT> &c, CT ux, CT uy, CT ux2, CT uy2,
+                                                 CT uxy, CT n2s, CT n2d, CT n11, CT gx, CT gy,
+                                                 CT &d2s, CT &d2d, CT &d11)
+{
+    // coefficients of eq. 46 (over rho): cbx = (P ux^2 + Q uy^2 + a1) / 2
+    // - 2 c2, csx = (P ux^2 - Q uy^2 + a1) / 2 - 2 c2 / omega_nu, likewise y
+    const CT cbx = c.hPg * ux2 + (c.hQg * uy2 + c.cbx0);
+    const CT cby = c.hPg * uy2 + (c.hQg * ux2 + c.cby0);
+    const CT csx = c.hPg * ux2 + (c.csx0 - c.hQg * uy2);
+    const CT csy = c.hQg * ux2 + (c.csy0 - c.hPg * uy2);
+    const CT Agx = c.Ab * ux * gx, Bgy = c.Bb * uy * gy;  // -e_b = Agx + Bgy
+    const CT R2s = n2s - (Agx + Bgy);
+    const CT R2d = n2d + (Bgy - Agx);
+    const CT det = cbx * csy - csx * cby;
+    const CT ip = recip(det * cby);
+    const CT Dx = (csy * R2s - cby * R2d) * (cby * ip);
+    const CT Dy = (R2s - cbx * Dx) * (det * ip);
+    const CT Ds = Dx + Dy;
+    d2s = CT(-2) * n2s - c.c2x2 * Ds;
+    d2d = CT(-2) * n2d - c.c4hnu * (Dx - Dy);
+    const CT cor11 = c.kq11 * uxy * Ds + c.kl11 * (uy * gx + ux * gy);
+    d11 = c.om_nu * (cor11 - n11);
+}
+
 // The method as the paper runs it (every correction, unit rates for the
 // non-hydrodynamic moments, no body force), written for few operations.
 // With omega_xi = omega_3 = omega_4 = 1 the post-collision k2s, k21, k12 and
-// k22 are their (corrected) equilibria, so the third- and fourth-order moments
-// of f are never needed: only rho, j and the raw second moments are formed,
-// and the second central moments follow from k20 = m20 - rho ux^2,
-// k02 = m02 - rho uy^2, k11 = m11 - rho ux uy.  After the collision the first
-// central moments are zero and j is unchanged, so the binomial shift back to
-// raw moments has closed forms; the raw moments of the deviations (those of
-// f minus rho0 (1,0,c2)x(1,0,c2)) then give the new deviations through
-// P^-1 S^-1.
+// k22 are their (corrected) equilibria, so no third- or fourth-order central
+// moment of f is needed: rho, j and the raw second moments give the second
+// central moments (k20 = m20 - rho ux^2, k02 = m02 - rho uy^2,
+// k11 = m11 - rho ux uy).  After the collision the first central moments are
+// zero and j is unchanged, so the binomial shift back to raw moments has
+// closed forms; the change of the raw moments goes back through P^-1 S^-1 and
+// is added to the stored deviations (incremental, as in collide()).
 template <typename CT>
 __device__ __forceinline__ void collide_plain(const Coef<CT> &c, CT d[9], CT gx, CT gy)
 {
@@ -253,8 +287,8 @@ __device__ __forceinline__ void collide_plain(const Coef<CT> &c, CT d[9], CT gx,
     const CT ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
     const CT u2s = ux2 + uy2;
 
-    // raw second moments of the deviations, then the central ones of f
-    // minus rho0 c2 (k20, k02) and k11
+    // raw second moments of the deviations (those of rho0 w are rho0 c2,
+    // rho0 c2, 0), then the central ones of f minus rho0 c2 (k20, k02), k11
     const CT m20 = (X2[0] + X2[1]) + X2[2];
     const CT m02 = c.r2 * (X0[2] + X0[0]);
     const CT m11 = c.r * (X1[2] - X1[0]);
@@ -270,49 +304,53 @@ __device__ __forceinline__ void collide_plain(const Coef<CT> &c, CT d[9], CT gx,
     const CT e2d = irh * (ux2 - uy2);
     const CT e11 = irh * uxy;
 
-    CT cor2s, cor2d, cor11;
-    corrections<CT, true>(c, ux, uy, ux2, uy2, uxy, k2s - e2s, k2d - e2d, gx, gy, cor2s, cor2d,
-                          cor11);
+    // changes of the second central moments in the collision, the same as
+    // those of the raw second moments
+    CT d2s, d2d, d11;
+    increments_plain(c, ux, uy, ux2, uy2, uxy, k2s - e2s, k2d - e2d, k11 - e11, gx, gy, d2s, d2d,
+                     d11);
+    const CT d20 = CT(0.5) * (d2s + d2d), d02 = CT(0.5) * (d2s - d2d);
 
-    // post-collision second central moments (omega_xi = 1: k2s takes its
-    // equilibrium), k20 and k02 minus rho0 c2
-    const CT K2s = e2s + cor2s;
-    const CT K2d = k2d + c.om_nu * ((e2d + cor2d) - k2d);
-    const CT K11 = k11 + c.om_nu * ((e11 + cor11) - k11);
-    const CT K20 = CT(0.5) * (K2s + K2d), K02 = CT(0.5) * (K2s - K2d);
+    // raw third and fourth moments after the collision from the central ones
+    // (k21 = g3 rho ux^2 uy, k12 = g3 rho ux uy^2, k22 = c2^2 rho), minus the
+    // raw moments before it (those of rho0 w: 0, 0, rho0 c2^2)
+    const CT A = (k20 + d20) + c.c2rho0, B = (k02 + d02) + c.c2rho0;  // k20, k02 of f
+    const CT K11 = k11 + d11;
+    const CT rg = c.g3p1 * rho;  // (g3 + 1) rho
+    const CT d21 = (uy * (rg * ux2 + A) + (ux + ux) * K11) - c.r * (X2[2] - X2[0]);
+    const CT d12 = (ux * (rg * uy2 + B) + (uy + uy) * K11) - c.r2 * (X1[2] + X1[0]);
+    const CT d22 = (((c.c2sq * drho + (c.g34p1 * rho) * (ux2 * uy2)) + (ux2 * B + uy2 * A)) +
+                    CT(4) * uxy * K11) -
+                   c.r2 * (X2[2] + X2[0]);
 
-    // raw moments of the new deviations from the central ones (first central
-    // moments zero, k21 = g3 rho ux^2 uy, k12 = g3 rho ux uy^2, k22 = c2^2 rho):
-    // m10, m01 are jx, jy as before the collision
-    const CT w20 = K20 + ux * jx;
-    const CT w02 = K02 + uy * jy;
-    const CT w11 = K11 + uy * jx;
-    const CT A = K20 + c.c2rho0, B = K02 + c.c2rho0;  // k20, k02 of f
-    const CT rg = c.g3p1 * rho;                      // (g3 + 1) rho
-    const CT w21 = uy * (rg * ux2 + A) + (ux + ux) * K11;
-    const CT w12 = ux * (rg * uy2 + B) + (uy + uy) * K11;
-    const CT w22 = ((c.c2sq * drho + (c.g34p1 * rho) * (ux2 * uy2)) + (ux2 * B + uy2 * A)) +
-                   CT(4) * uxy * K11;
-
-    // y-transform back for each x-moment, halved (the halves of the
-    // x-transform folded in) ...
+    // f~ = f + P^-1 S^-1 dm (dm00 = dm10 = dm01 = 0): y-transform back for
+    // each x-moment, halved (the halves of the x-transform folded in) ...
     CT G[3][3];  // [x-moment][e_y + 1]
-    auto yinv = [&](CT K0, CT K1, CT K2, CT *g) {
-        const CT a = c.qinv_r * K1, b = c.qinv_r2 * K2;  // 1/(4r), 1/(4r^2)
-        g[0] = b - a;
-        g[1] = CT(0.5) * K0 - CT(2) * b;
-        g[2] = b + a;
-    };
-    yinv(drho, jy, w02, G[0]);
-    yinv(jx, w11, w12, G[1]);
-    yinv(w20, w21, w22, G[2]);
-    // ... then the x-transform back for each row
+    {
+        const CT b = c.qinv_r2 * d02;
+        G[0][0] = b;
+        G[0][1] = CT(-2) * b;
+        G[0][2] = b;
+    }
+    {
+        const CT a = c.qinv_r * d11, b = c.qinv_r2 * d12;
+        G[1][0] = b - a;
+        G[1][1] = CT(-2) * b;
+        G[1][2] = b + a;
+    }
+    {
+        const CT a = c.qinv_r * d21, b = c.qinv_r2 * d22;
+        G[2][0] = b - a;
+        G[2][1] = CT(0.5) * d20 - CT(2) * b;
+        G[2][2] = b + a;
+    }
+    // ... then the x-transform back for each row, added to the populations
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
         const CT K0 = G[0][j], K1 = G[1][j], K2 = G[2][j];
-        q[j][0] = K2 - K1;
-        q[j][1] = CT(2) * (K0 - K2);
-        q[j][2] = K2 + K1;
+        q[j][0] += K2 - K1;
+        q[j][1] += CT(2) * (K0 - K2);
+        q[j][2] += K2 + K1;
     }
 #pragma unroll
     for (int a = 0; a < 9; ++a) d[a] = q[QJ[a]][QI[a]];

@@ -185,10 +185,14 @@ __device__ __forceinline__ void pull_checked(const Coef<typename Mem<ST>::CT> &c
     }
 }
 
+// Sum of the nine populations, row by row of the velocity set (e_y = -1, 0,
+// +1) and within a row the two moving ones first: the same operations as the
+// density inside the collision, so that a thread that needs both computes it
+// once.
 template <typename CT>
 __device__ __forceinline__ CT sum9(const CT d[9])
 {
-    return ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
+    return (((d[8] + d[7]) + d[4]) + ((d[1] + d[3]) + d[0])) + ((d[5] + d[6]) + d[2]);
 }
 
 // Hydrodynamic fields of streamed deviations (eq. hydrodynamicfields):
