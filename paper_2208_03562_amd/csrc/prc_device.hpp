@@ -166,6 +166,7 @@ __device__ __forceinline__ void pull_checked(const Coef<typename Mem<ST>::CT> &c
 {
     using CT = typename Mem<ST>::CT;
     constexpr uint32_t E = sizeof(ST);
+    const uint32_t own = (uint32_t)y * c.row_bytes + (uint32_t)x * E;
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
         int sx = x - EX[a], sy = y - EY[a];
@@ -174,14 +175,13 @@ __device__ __forceinline__ void pull_checked(const Coef<typename Mem<ST>::CT> &c
         else out |= (sx < 0) | (sx >= c.nx);
         if (Bc<BC>::wrap_y) sy = wrap(sy, c.ny);
         else out |= (sy < 0) | (sy >= c.ny);
-        if (!out) {
-            d[a] = Mem<ST>::ld(rs, (uint32_t)sy * c.row_bytes + (uint32_t)sx * E, a * c.plane_bytes);
-        } else {
-            CT v = Mem<ST>::ld(rs, (uint32_t)y * c.row_bytes + (uint32_t)x * E,
-                                OPP[a] * c.plane_bytes);
-            if (Bc<BC>::lid && LIDC[a] != 0 && sy >= c.ny) v += CT(LIDC[a]) * c.lid;
-            d[a] = v;
-        }
+        // the whole offset in the vector register (a per-lane choice of the
+        // scalar plane offset would make the compiler loop over its values)
+        const uint32_t off = out ? own + OPP[a] * c.plane_bytes
+                                 : (uint32_t)sy * c.row_bytes + (uint32_t)sx * E + a * c.plane_bytes;
+        CT v = Mem<ST>::ld(rs, off, 0);
+        if (Bc<BC>::lid && LIDC[a] != 0) v = sy >= c.ny ? v + CT(LIDC[a]) * c.lid : v;
+        d[a] = v;
     }
 }
 
