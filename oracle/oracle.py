@@ -64,6 +64,8 @@ def lib():
         dp = ctypes.POINTER(ctypes.c_double)
         pp = ctypes.POINTER(Params)
         L.orc_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_set_threads.restype = None
         L.orc_lattice.argtypes = [ctypes.c_double, dp, dp]
         L.orc_omega_nu_from_re.argtypes = [pp, ctypes.c_double]
         L.orc_omega_nu_from_re.restype = ctypes.c_double
@@ -117,6 +119,11 @@ def with_re(p: Params, re: float) -> Params:
 
 def threads() -> int:
     return int(lib().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    """Use n threads in the oracle's parallel loops from now on."""
+    lib().orc_set_threads(int(n))
 
 
 def lattice(r: float):

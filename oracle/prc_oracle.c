@@ -53,6 +53,15 @@ int orc_threads(void)
 #endif
 }
 
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 void orc_lattice(double r, double *q, double *c2)
 {
     /* eq. 2: c_s = q c_*, q = min(1, r); c_*^2 = 1/3 (eq. 1) */

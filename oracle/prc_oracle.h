@@ -58,6 +58,8 @@ typedef struct {
 
 /* threads the loops over nodes may use (OpenMP), 1 without OpenMP */
 int orc_threads(void);
+/* Threads the parallel loops use from now on (n > 0; no effect without OpenMP). */
+void orc_set_threads(int n);
 
 /* Sec. 2, eq. 2: q = min(1, r), c_s^2 = q^2 c_*^2 with c_*^2 = 1/3 */
 void orc_lattice(double r, double *q, double *c2);
