@@ -48,8 +48,8 @@ struct Coef {
     CT mhxi, mhnu;          // -(1/omega_xi - 1/2), -(1/omega_nu - 1/2)
     CT mhxi2, mhnu2;        // twice those (density-gradient terms)
     CT kq11, kl11;          // k11 corrections: -Q_gamma h_nu, -(1/gamma - 1) h_nu c2
-    CT hPg, hQg;            // P_gamma / 2, Q_gamma / 2
-    CT cbx0, cby0, csx0, csy0;  // a1/2 + cb0, a2/2 + cb0, a1/2 - cs0, cs0 - a2/2
+    CT sPQ, dPQ;            // (P_gamma + Q_gamma)/4, (P_gamma - Q_gamma)/4
+    CT sa0, sb0, sc0, se0;  // constant parts of the strain system for Dx +- Dy
     CT c4hnu;               // 4 c2 h_nu
     CT om_nu, om_xi, om_3, om_4;
     CT fxh, fyh;            // F / (2 gamma) (eq. hydrodynamicfields)
@@ -115,12 +115,22 @@ inline Coef<CT> make_coef(const prc_params &p, int64_t row_stride, int64_t plane
     c.mhnu2 = CT(-2.0 * hnu);
     c.kq11 = CT(-Qg * hnu);
     c.kl11 = CT(-(1.0 / g - 1.0) * hnu * c2);
-    c.hPg = CT(0.5 * (4.0 / (g * g) - 1.0 / g));
-    c.hQg = CT(0.5 * Qg);
-    c.cbx0 = CT(0.5 * (3.0 * c2 - 1.0) - 2.0 * c2 / p.omega_xi);
-    c.cby0 = CT(0.5 * (3.0 * c2 - r * r) - 2.0 * c2 / p.omega_xi);
-    c.csx0 = CT(0.5 * (3.0 * c2 - 1.0) - 2.0 * c2 / p.omega_nu);
-    c.csy0 = CT(2.0 * c2 / p.omega_nu - 0.5 * (3.0 * c2 - r * r));
+    {
+        // coefficients of eq. 46 over rho: cbx = (P ux^2 + Q uy^2 + a1)/2 + cb0,
+        // cby = (P uy^2 + Q ux^2 + a2)/2 + cb0, csx = (P ux^2 - Q uy^2 + a1)/2 - cs0,
+        // csy = cs0 - (P uy^2 - Q ux^2 + a2)/2; their half sums and differences
+        // are linear in ux^2 + uy^2 and ux^2 - uy^2
+        const double Pg = 4.0 / (g * g) - 1.0 / g, cb0 = -2.0 * c2 / p.omega_xi;
+        const double cs0 = 2.0 * c2 / p.omega_nu;
+        const double bx0 = 0.5 * (3.0 * c2 - 1.0) + cb0, by0 = 0.5 * (3.0 * c2 - r * r) + cb0;
+        const double sx0 = 0.5 * (3.0 * c2 - 1.0) - cs0, sy0 = cs0 - 0.5 * (3.0 * c2 - r * r);
+        c.sPQ = CT(0.25 * (Pg + Qg));
+        c.dPQ = CT(0.25 * (Pg - Qg));
+        c.sa0 = CT(0.5 * (bx0 + by0));
+        c.sb0 = CT(0.5 * (bx0 - by0));
+        c.sc0 = CT(0.5 * (sx0 + sy0));
+        c.se0 = CT(0.5 * (sx0 - sy0));
+    }
     c.c4hnu = CT(4.0 * c2 * hnu);
     c.om_nu = CT(p.omega_nu);
     c.om_xi = CT(p.omega_xi);

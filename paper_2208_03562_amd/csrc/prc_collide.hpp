@@ -230,28 +230,30 @@ __device__ __forceinline__ void collide(const Coef<CT> &c, CT d[9], CT gx, CT gy
 //   k2d: -2 h_nu (n2d + (2 c2 / omega_nu) (Dx - Dy)),
 // so that relaxing with omega_xi = 1 and omega_nu gives the changes
 //   d2s = -2 n2s - 2 c2 (Dx + Dy),  d2d = -2 n2d - 4 c2 h_nu (Dx - Dy)
-// (the same terms as in corrections(), summed in closed form).
+// (the same terms as in corrections(), summed in closed form).  Only
+// Ds = Dx + Dy and Dm = Dx - Dy are needed, so the system is solved for them:
+// its coefficients are linear in ux^2 + uy^2 and ux^2 - uy^2.
 template <typename CT>
-__device__ __forceinline__ void increments_plain(const Coef<CT> &c, CT ux, CT uy, CT ux2, CT uy2,
+__device__ __forceinline__ void increments_plain(const Coef<CT> &c, CT ux, CT uy, CT u2s, CT u2d,
                                                  CT uxy, CT n2s, CT n2d, CT n11, CT gx, CT gy,
                                                  CT &d2s, CT &d2d, CT &d11)
 {
-    // coefficients of eq. 46 (over rho): cbx = (P ux^2 + Q uy^2 + a1) / 2
-    // - 2 c2, csx = (P ux^2 - Q uy^2 + a1) / 2 - 2 c2 / omega_nu, likewise y
-    const CT cbx = c.hPg * ux2 + (c.hQg * uy2 + c.cbx0);
-    const CT cby = c.hPg * uy2 + (c.hQg * ux2 + c.cby0);
-    const CT csx = c.hPg * ux2 + (c.csx0 - c.hQg * uy2);
-    const CT csy = c.hQg * ux2 + (c.csy0 - c.hPg * uy2);
+    // a Ds + b Dm = R2s, cc Ds + e Dm = R2d with a = (cbx + cby)/2,
+    // b = (cbx - cby)/2, cc = (csx + csy)/2, e = (csx - csy)/2, where
+    // cbx = (P ux^2 + Q uy^2 + a1)/2 - 2 c2, csx = (P ux^2 - Q uy^2 + a1)/2
+    // - 2 c2/omega_nu, likewise along y
+    const CT a = c.sPQ * u2s + c.sa0;
+    const CT b = c.dPQ * u2d + c.sb0;
+    const CT cc = c.sPQ * u2d + c.sc0;
+    const CT e = c.dPQ * u2s + c.se0;
     const CT Agx = c.Ab * ux * gx, Bgy = c.Bb * uy * gy;  // -e_b = Agx + Bgy
     const CT R2s = n2s - (Agx + Bgy);
     const CT R2d = n2d + (Bgy - Agx);
-    const CT det = cbx * csy - csx * cby;
-    const CT ip = recip(det * cby);
-    const CT Dx = (csy * R2s - cby * R2d) * (cby * ip);
-    const CT Dy = (R2s - cbx * Dx) * (det * ip);
-    const CT Ds = Dx + Dy;
+    const CT idet = recip(a * e - b * cc);
+    const CT Ds = (R2s * e - b * R2d) * idet;
+    const CT Dm = (a * R2d - cc * R2s) * idet;
     d2s = CT(-2) * n2s - c.c2x2 * Ds;
-    d2d = CT(-2) * n2d - c.c4hnu * (Dx - Dy);
+    d2d = CT(-2) * n2d - c.c4hnu * Dm;
     const CT cor11 = c.kq11 * uxy * Ds + c.kl11 * (uy * gx + ux * gy);
     d11 = c.om_nu * (cor11 - n11);
 }
@@ -299,15 +301,16 @@ __device__ __forceinline__ void collide_plain(const Coef<CT> &c, CT d[9], CT gx,
     const CT k2d = k20 - k02;
 
     // preconditioned equilibria (eq. 14), minus the same constants
+    const CT u2d = ux2 - uy2;
     const CT irh = c.ig1 * rho;
     const CT e2s = c.c2x2 * drho + irh * u2s;
-    const CT e2d = irh * (ux2 - uy2);
+    const CT e2d = irh * u2d;
     const CT e11 = irh * uxy;
 
     // changes of the second central moments in the collision, the same as
     // those of the raw second moments
     CT d2s, d2d, d11;
-    increments_plain(c, ux, uy, ux2, uy2, uxy, k2s - e2s, k2d - e2d, k11 - e11, gx, gy, d2s, d2d,
+    increments_plain(c, ux, uy, u2s, u2d, uxy, k2s - e2s, k2d - e2d, k11 - e11, gx, gy, d2s, d2d,
                      d11);
     const CT d20 = CT(0.5) * (d2s + d2d), d02 = CT(0.5) * (d2s - d2d);
 

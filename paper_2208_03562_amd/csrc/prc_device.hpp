@@ -156,15 +156,16 @@ __device__ __forceinline__ void pull_inner(const Coef<typename Mem<ST>::CT> &c, 
     d[8] = Mem<ST>::ld(rs, rN, 8 * pb);             // from (x-1, y+1)
 }
 
-// Streaming with boundaries for any node (x, y) of the grid.  A source
-// outside a wall means half-way bounce-back: the population that left this
-// node along opp(a) returns along a; a source above the top row crosses the
-// lid and picks up the wall momentum term (top corners included).
+// Streaming with boundaries for any node (x, y) of the grid, loads only.  A
+// source outside a wall means half-way bounce-back: the population that left
+// this node along opp(a) returns along a.  A source above the top row also
+// crosses the lid, whose momentum term add_lid() adds once the loads are in
+// flight (a use of a loaded value right after its load would make the next
+// node's loads wait for it).
 template <typename ST, int BC>
-__device__ __forceinline__ void pull_checked(const Coef<typename Mem<ST>::CT> &c, rsrc_t rs,
-                                             int x, int y, typename Mem<ST>::CT d[9])
+__device__ __forceinline__ void pull_checked_ld(const Coef<typename Mem<ST>::CT> &c, rsrc_t rs,
+                                                int x, int y, typename Mem<ST>::CT d[9])
 {
-    using CT = typename Mem<ST>::CT;
     constexpr uint32_t E = sizeof(ST);
     const uint32_t own = (uint32_t)y * c.row_bytes + (uint32_t)x * E;
 #pragma unroll
@@ -179,10 +180,29 @@ __device__ __forceinline__ void pull_checked(const Coef<typename Mem<ST>::CT> &c
         // scalar plane offset would make the compiler loop over its values)
         const uint32_t off = out ? own + OPP[a] * c.plane_bytes
                                  : (uint32_t)sy * c.row_bytes + (uint32_t)sx * E + a * c.plane_bytes;
-        CT v = Mem<ST>::ld(rs, off, 0);
-        if (Bc<BC>::lid && LIDC[a] != 0) v = sy >= c.ny ? v + CT(LIDC[a]) * c.lid : v;
-        d[a] = v;
+        d[a] = Mem<ST>::ld(rs, off, 0);
     }
+}
+
+// Lid term of the populations a node of row y streamed across the top wall:
+// the two diagonal ones of the top row (f_7 = f~_5 - lid, f_8 = f~_6 + lid;
+// f_4 = f~_2 takes none), the top corners included.
+template <int BC, typename CT>
+__device__ __forceinline__ void add_lid(const Coef<CT> &c, int y, CT d[9])
+{
+    if (Bc<BC>::lid) {
+        const bool top = y >= c.ny - 1;
+        d[7] = top ? d[7] + CT(LIDC[7]) * c.lid : d[7];
+        d[8] = top ? d[8] + CT(LIDC[8]) * c.lid : d[8];
+    }
+}
+
+template <typename ST, int BC>
+__device__ __forceinline__ void pull_checked(const Coef<typename Mem<ST>::CT> &c, rsrc_t rs,
+                                             int x, int y, typename Mem<ST>::CT d[9])
+{
+    pull_checked_ld<ST, BC>(c, rs, x, y, d);
+    add_lid<BC>(c, y, d);
 }
 
 // Sum of the nine populations, row by row of the velocity set (e_y = -1, 0,

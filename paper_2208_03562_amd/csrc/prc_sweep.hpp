@@ -53,11 +53,11 @@ __device__ __forceinline__ void tile_load(const Coef<typename Mem<ST>::CT> &c, r
         if (g.ring) pull_inner<ST>(c, rs, (uint32_t)ry * c.row_bytes + (uint32_t)(rx - 1) * E, e);
     } else {
         fix_coord<BC>(x, y, c.nx, c.ny);  // slots beyond the grid stand in for their image
-        pull_checked<ST, BC>(c, rs, x, y, d);
-        if (g.ring) {
-            fix_coord<BC>(rx, ry, c.nx, c.ny);
-            pull_checked<ST, BC>(c, rs, rx, ry, e);
-        }
+        fix_coord<BC>(rx, ry, c.nx, c.ny);
+        pull_checked_ld<ST, BC>(c, rs, x, y, d);
+        if (g.ring) pull_checked_ld<ST, BC>(c, rs, rx, ry, e);
+        add_lid<BC>(c, y, d);
+        if (g.ring) add_lid<BC>(c, ry, e);
     }
 }
 

@@ -134,37 +134,81 @@ __device__ __forceinline__ void sweep2_tile(const Coef<typename Mem<ST>::CT> &c,
     const rsrc_t rs = make_rsrc(src, c.state_bytes);
     // every source of every slot of R3 lies inside the grid
     const bool inner = x0 >= 4 && y0 >= 4 && x0 + TX + 4 <= c.nx && y0 + TY + 4 <= c.ny;
-    auto pull1 = [&](int i, int j, CT d[9]) {
+    auto load1 = [&](int i, int j, CT d[9]) {
         if (inner) {
             pull_inner<ST>(c, rs, (uint32_t)(y0 + j) * c.row_bytes + (uint32_t)(x0 + i - 1) * E, d);
         } else {
             int x = x0 + i, y = y0 + j;
             fix_coord<BC>(x, y, c.nx, c.ny);
-            pull_checked<ST, BC>(c, rs, x, y, d);
+            pull_checked_ld<ST, BC>(c, rs, x, y, d);
         }
     };
-
-    // step 1: streaming and densities over R3; R2 populations kept for the
-    // collision
-    CT keep[R::S2][9];
-#pragma unroll
-    for (int s = 0; s < R::S2; ++s) {
-        const int k = t + s * R::T;
-        if (k < R::N2) {
-            const int i = k % R::W2 - 2, j = k / R::W2 - 2;
-            pull1(i, j, keep[s]);
-            D1[j + 3][i + 3] = sum9(keep[s]);
+    auto finish1 = [&](int i, int j, CT d[9]) {  // lid term, density
+        if (!inner) {
+            int x = x0 + i, y = y0 + j;
+            fix_coord<BC>(x, y, c.nx, c.ny);
+            add_lid<BC>(c, y, d);
         }
-    }
+        D1[j + 3][i + 3] = sum9(d);
+    };
+
+    // step 1: streaming and densities over R3; the R2 populations are kept
+    // for the collision.  Workgroups of up to 512 threads issue every load of
+    // the region before the first use; 1024-thread workgroups finish one slot
+    // before loading the next, which measured faster for them (and slower for
+    // the smaller ones) on cache-resident and HBM grids alike.
+    constexpr bool kEager = R::T <= 512;
+    CT keep[R::S2][9];
+    if constexpr (kEager) {
+        CT ring[R::SB][9];
 #pragma unroll
-    for (int s = 0; s < R::SB; ++s) {
-        const int k = t + s * R::T;
-        if (k < R::NB) {
-            int i, j;
-            ring3_pos<TX, TY>(k, i, j);
-            CT d[9];
-            pull1(i, j, d);
-            D1[j + 3][i + 3] = sum9(d);
+        for (int s = 0; s < R::SB; ++s) {
+            const int k = t + s * R::T;
+            if (k < R::NB) {
+                int i, j;
+                ring3_pos<TX, TY>(k, i, j);
+                load1(i, j, ring[s]);
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < R::S2; ++s) {
+            const int k = t + s * R::T;
+            if (k < R::N2) load1(k % R::W2 - 2, k / R::W2 - 2, keep[s]);
+        }
+#pragma unroll
+        for (int s = 0; s < R::SB; ++s) {
+            const int k = t + s * R::T;
+            if (k < R::NB) {
+                int i, j;
+                ring3_pos<TX, TY>(k, i, j);
+                finish1(i, j, ring[s]);
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < R::S2; ++s) {
+            const int k = t + s * R::T;
+            if (k < R::N2) finish1(k % R::W2 - 2, k / R::W2 - 2, keep[s]);
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < R::S2; ++s) {
+            const int k = t + s * R::T;
+            if (k < R::N2) {
+                const int i = k % R::W2 - 2, j = k / R::W2 - 2;
+                load1(i, j, keep[s]);
+                finish1(i, j, keep[s]);
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < R::SB; ++s) {
+            const int k = t + s * R::T;
+            if (k < R::NB) {
+                int i, j;
+                ring3_pos<TX, TY>(k, i, j);
+                CT d[9];
+                load1(i, j, d);
+                finish1(i, j, d);
+            }
         }
     }
     __syncthreads();
@@ -191,13 +235,11 @@ __device__ __forceinline__ void sweep2_tile(const Coef<typename Mem<ST>::CT> &c,
     // every source of every slot of R1 lies inside the grid
     const bool inner2 = x0 >= 2 && y0 >= 2 && x0 + TX + 2 <= c.nx && y0 + TY + 2 <= c.ny;
     if (inner2) {
+        CT e[9];
         pull_lds_inner<ST, TX, TY>(P1, g.tx, g.ty, d);
+        if (g.ring) pull_lds_inner<ST, TX, TY>(P1, g.hx, g.hy, e);
         D2[g.ty + 1][g.tx + 1] = sum9(d);
-        if (g.ring) {
-            CT e[9];
-            pull_lds_inner<ST, TX, TY>(P1, g.hx, g.hy, e);
-            D2[g.hy + 1][g.hx + 1] = sum9(e);
-        }
+        if (g.ring) D2[g.hy + 1][g.hx + 1] = sum9(e);
     } else {
         {
             int x, y, hi, hj;
