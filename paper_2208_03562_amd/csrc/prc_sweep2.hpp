@@ -154,9 +154,9 @@ __device__ __forceinline__ void sweep2_tile(const Coef<typename Mem<ST>::CT> &c,
 
     // step 1: streaming and densities over R3; the R2 populations are kept
     // for the collision.  Workgroups of up to 512 threads issue every load of
-    // the region before the first use; 1024-thread workgroups finish one slot
-    // before loading the next, which measured faster for them (and slower for
-    // the smaller ones) on cache-resident and HBM grids alike.
+    // the region before the first use; 1024-thread workgroups load the ring
+    // only after the densities of R2, which measured faster for them (and
+    // slower for the smaller ones) on cache-resident and HBM grids alike.
     constexpr bool kEager = R::T <= 512;
     CT keep[R::S2][9];
     if constexpr (kEager) {
@@ -193,11 +193,12 @@ __device__ __forceinline__ void sweep2_tile(const Coef<typename Mem<ST>::CT> &c,
 #pragma unroll
         for (int s = 0; s < R::S2; ++s) {
             const int k = t + s * R::T;
-            if (k < R::N2) {
-                const int i = k % R::W2 - 2, j = k / R::W2 - 2;
-                load1(i, j, keep[s]);
-                finish1(i, j, keep[s]);
-            }
+            if (k < R::N2) load1(k % R::W2 - 2, k / R::W2 - 2, keep[s]);
+        }
+#pragma unroll
+        for (int s = 0; s < R::S2; ++s) {
+            const int k = t + s * R::T;
+            if (k < R::N2) finish1(k % R::W2 - 2, k / R::W2 - 2, keep[s]);
         }
 #pragma unroll
         for (int s = 0; s < R::SB; ++s) {
