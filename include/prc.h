@@ -186,8 +186,12 @@ prc_status prc_solve(const prc_params *p, void *f_a, void *f_b, double *u_prev,
  * every later sweep of a problem with the same storage, boundaries and grid
  * size in this process.  The tile shape changes only the speed, not the
  * results.  tile_out (host, may be NULL) receives the chosen index.  Without
- * a tuning call the library picks 128 x 4 for grids at least 256 nodes wide
- * and 64 x 4 otherwise.  Synchronises the stream; PRC_EHIP if the scratch
+ * a tuning call the library picks, for FP32 and 16-bit grids at least 256 x 64
+ * nodes, 64 x 16 two-step tiles (7) when the two states fit 160 MB or the
+ * storage is 16-bit and 64 x 8 two-step tiles (5) otherwise; for other grids
+ * and FP64, 128 x 4 (2) when at least 256 nodes wide and 64 x 4 (0)
+ * otherwise.  The environment variable PRC_TILE, read once, forces a shape
+ * where it is allowed.  Synchronises the stream; PRC_EHIP if the scratch
  * allocation fails. */
 prc_status prc_tune(const prc_params *p, int32_t *tile_out, hipStream_t stream);
 

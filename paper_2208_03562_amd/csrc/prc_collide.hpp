@@ -23,6 +23,12 @@
 //    eq. 48; the coefficients of eq. 46 all carry a factor rho, so the solve
 //    is done for rho dxux, rho dyuy directly and rho never appears.
 //
+// collide_plain is the method exactly as the paper runs it (every correction,
+// unit rates for the non-hydrodynamic moments, no body force) with fewer
+// operations: only the second central moments are formed, the correction
+// terms are summed in closed form through the strain-rate equations, and the
+// change of the raw moments is added to the stored deviations.
+//
 // collide_raw is the same update with the moments relaxed in the rest frame
 // (raw moments, the PRNR-LBM of Sec. 4.1 used for comparison in Sec. 6): raw
 // equilibria of eq. 12, raw sources of eq. 13, the same corrections.

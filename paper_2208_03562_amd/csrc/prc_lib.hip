@@ -86,10 +86,17 @@ static int tile_choice(const prc_params &p)
         auto it = g_tuned.find(tune_key(p));
         if (it != g_tuned.end()) return it->second;
     }
-    // measured on MI355X: two steps per launch pays for FP32 on grids that
-    // fill the chip; 16-bit storage is bound by arithmetic, where the extra
-    // ring collisions of the two-step shapes cost more than they save
-    if (p.storage == PRC_F32 && p.nx >= 256 && p.ny >= 64) return 8;
+    // measured on MI355X: on grids that fill the chip two steps per launch
+    // pay for FP32 and 16-bit storage alike; 1024-thread tiles (64 x 16) are
+    // fastest while the two states stay in the last-level cache and for
+    // 16-bit storage, 512-thread tiles (64 x 8) for FP32 states streamed
+    // from HBM
+    if (p.storage != PRC_F64 && p.nx >= 256 && p.ny >= 64) {
+        int64_t row, plane, total;
+        layout(p, row, plane, total);
+        const bool cached = 2 * total * (int64_t)elem_bytes(p.storage) <= kNtPairBytes;
+        return (cached || p.storage != PRC_F32) ? 7 : 5;
+    }
     return p.nx >= 256 ? 2 : 0;
 }
 
