@@ -1,9 +1,9 @@
-// Two time steps per launch (temporal blocking) for states that live in the
-// last-level cache.
+// Two time steps per launch (temporal blocking).
 //
-// A single step per launch makes every node's data cross the cache boundary
-// twice per step, and a launch over a cache-resident grid is one wave of
-// workgroups whose loads, collisions and stores hardly overlap.  Here a
+// A single step per launch moves the whole state through memory every step
+// (HBM, or the last-level cache for a small state), and a launch over a
+// cache-resident grid is one wave of workgroups whose loads, collisions and
+// stores hardly overlap.  Here a
 // workgroup produces its tile two steps ahead from the state three rings
 // further out, keeping the intermediate step in LDS:
 //
