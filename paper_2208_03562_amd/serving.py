@@ -72,6 +72,8 @@ def summary(served: list[Served]) -> dict:
     for s in served:
         by[s.status] = by.get(s.status, 0) + 1
     names = {0: "converged", 1: "max_steps", -3: "diverged", -1: "rejected"}
+    # last relative residual of the requests that ran to their step budget
+    res = np.array([s.residual for s in served if s.status == 1 and np.isfinite(s.residual)])
     return {
         "requests": len(served),
         "outcomes": {names.get(k, str(k)): v for k, v in sorted(by.items())},
@@ -81,4 +83,5 @@ def summary(served: list[Served]) -> dict:
         "latency_p99_s": float(np.percentile(lat, 99)),
         "latency_max_s": float(lat.max()),
         "span_s": span,
+        "budget_residual_p50": float(np.median(res)) if res.size else None,
     }
