@@ -43,7 +43,7 @@ namespace prc {
 // n2s = k2s - k2s_eq and n2d = k2d - k2d_eq (the same in the central and the
 // raw frame).  The solve is done for rho dxux, rho dyuy: the coefficients of
 // eq. 46 all carry a factor rho, so rho never appears.
-template <typename CT, bool ALL>
+template <typename CT>
 __device__ __forceinline__ void corrections(const Coef<CT> &c, CT ux, CT uy, CT ux2, CT uy2, CT uxy,
                                             CT n2s, CT n2d, CT gx, CT gy, CT &cor2s, CT &cor2d,
                                             CT &cor11)
@@ -51,7 +51,7 @@ __device__ __forceinline__ void corrections(const Coef<CT> &c, CT ux, CT uy, CT 
     cor2s = CT(0);
     cor2d = CT(0);
     cor11 = CT(0);
-    const int corr = ALL ? PRC_CORR_ALL : c.corr;
+    const int corr = c.corr;
     if (!corr) return;
     // bx = P ux^2 + Q uy^2 + a1, sx = P ux^2 - Q uy^2 + a1 (likewise by, sy)
     const CT tx = c.Pg * ux2 + c.a1, ty = c.Pg * uy2 + c.a2;
@@ -85,11 +85,9 @@ __device__ __forceinline__ void corrections(const Coef<CT> &c, CT ux, CT uy, CT 
         cor11 = c.kq11 * uxy * (Dx + Dy) + c.kl11 * (uy * gx + ux * gy);
 }
 
-// FORCE: the body force may be nonzero.  ALL: the method as the paper runs
-// it -- every correction term on and unit rates for the non-hydrodynamic
-// moments (omega_xi = omega_1 = omega_3 = omega_4 = 1, Appendix A); otherwise
-// the correction bitmask and all rates are read at run time.
-template <typename CT, bool FORCE, bool ALL>
+// The general central-moment collision: the correction bitmask and all rates
+// are read at run time.  FORCE: the body force may be nonzero.
+template <typename CT, bool FORCE>
 __device__ __forceinline__ void collide(const Coef<CT> &c, CT d[9], CT gx, CT gy)
 {
     CT q[3][3];  // [e_y + 1][e_x + 1]
@@ -158,11 +156,10 @@ __device__ __forceinline__ void collide(const Coef<CT> &c, CT d[9], CT gx, CT gy
 
     // corrections (eq. 38-40) with the local strain rates (eq. 43-48)
     CT cor2s, cor2d, cor11;
-    corrections<CT, ALL>(c, ux, uy, ux2, uy2, uxy, k2s - e2s, k2d - e2d, gx, gy, cor2s, cor2d,
-                         cor11);
+    corrections<CT>(c, ux, uy, ux2, uy2, uxy, k2s - e2s, k2d - e2d, gx, gy, cor2s, cor2d, cor11);
 
     // moment increments of the relaxation (Appendix A), B^-1 folded in
-    CT d2s = ALL ? (e2s + cor2s) - k2s : c.om_xi * ((e2s + cor2s) - k2s);
+    CT d2s = c.om_xi * ((e2s + cor2s) - k2s);
     CT d2d = c.om_nu * ((e2d + cor2d) - k2d);
     CT d11 = c.om_nu * ((e11 + cor11) - k11);
     if (FORCE) {
@@ -172,9 +169,9 @@ __device__ __forceinline__ void collide(const Coef<CT> &c, CT d[9], CT gx, CT gy
         d11 += c.snu * (c.qfx * uy + c.qfy * ux);
     }
     const CT g3r = c.g3 * rho;
-    const CT d21 = ALL ? g3r * ux2 * uy - k21 : c.om_3 * (g3r * ux2 * uy - k21);
-    const CT d12 = ALL ? g3r * ux * uy2 - k12 : c.om_3 * (g3r * ux * uy2 - k12);
-    const CT d22 = ALL ? c.c2sq * drho - k22 : c.om_4 * (c.c2sq * drho - k22);
+    const CT d21 = c.om_3 * (g3r * ux2 * uy - k21);
+    const CT d12 = c.om_3 * (g3r * ux * uy2 - k12);
+    const CT d22 = c.om_4 * (c.c2sq * drho - k22);
     const CT d2sum = d2s + d2d;
     const CT d20 = CT(0.5) * d2sum, d20h = CT(0.25) * d2sum;
     const CT d02 = CT(0.5) * (d2s - d2d);
@@ -415,8 +412,7 @@ __device__ __forceinline__ void collide_raw(const Coef<CT> &c, CT d[9], CT gx, C
     const CT e11 = igr * uxy;
 
     CT cor2s, cor2d, cor11;
-    corrections<CT, false>(c, ux, uy, ux2, uy2, uxy, m2s - e2s, m2d - e2d, gx, gy, cor2s, cor2d,
-                           cor11);
+    corrections<CT>(c, ux, uy, ux2, uy2, uxy, m2s - e2s, m2d - e2d, gx, gy, cor2s, cor2d, cor11);
 
     CT d2s = c.om_xi * ((e2s + cor2s) - m2s);
     CT d2d = c.om_nu * ((e2d + cor2d) - m2d);

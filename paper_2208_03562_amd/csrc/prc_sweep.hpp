@@ -89,15 +89,14 @@ __device__ __forceinline__ void density_gradient(const Coef<CT> &c, const CT (*D
 template <typename CT, bool FORCE, bool ALL>
 __device__ __forceinline__ void collide_node(const Coef<CT> &c, CT d[9], CT gx, CT gy)
 {
-    if constexpr (ALL && !FORCE) {
+    if constexpr (ALL) {
+        static_assert(!FORCE, "the method as published has no body force");
         collide_plain<CT>(c, d, gx, gy);
-    } else if constexpr (ALL) {
-        collide<CT, FORCE, ALL>(c, d, gx, gy);
     } else {
         if (c.frame == PRC_FRAME_RAW)
             collide_raw<CT, FORCE>(c, d, gx, gy);
         else
-            collide<CT, FORCE, ALL>(c, d, gx, gy);
+            collide<CT, FORCE>(c, d, gx, gy);
     }
 }
 
