@@ -440,7 +440,8 @@ def main():
     if args.hbm_steps > 0:
         for wh in (workloads.CAVITY_4096x2048_F32, workloads.CAVITY_4096x2048_MA002["f32"],
                    workloads.CAVITY_4096x2048_MA002["f16"],
-                   workloads.CAVITY_4096x2048_MA002["bf16"]):
+                   workloads.CAVITY_4096x2048_MA002["bf16"],
+                   workloads.CAVITY_4096x2048_MA002["f64"]):
             r = run_gpu(wh, args.hbm_steps, min(args.warmup, 500))
             big[wh.name] = dict(
                 workload=wh.name, u_lid=round(wh.u_lid, 6), mlups=round(r["mlups"], 1),

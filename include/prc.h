@@ -179,18 +179,18 @@ prc_status prc_solve(const prc_params *p, void *f_a, void *f_b, double *u_prev,
 /* Autotuner: time every tile shape of the sweep kernel (threads along x by
  * along y: 0 = 64 x 4, 1 = 64 x 8, 2 = 128 x 4, 3 = 32 x 8, 4 = 32 x 16, one
  * time step per launch; 5 = 64 x 8, 6 = 32 x 16, 7 = 64 x 16, 8 = 32 x 32, two
- * time steps per launch with the intermediate state in LDS, FP32 and 16-bit
- * storage only; see prc_tile_info) for this problem's storage,
+ * time steps per launch with the intermediate state in LDS; see
+ * prc_tile_info) for this problem's storage,
  * boundaries and grid size, on two scratch state buffers that the call
  * allocates and frees itself (hipMalloc/hipFree), and use the fastest (per time step) for
  * every later sweep of a problem with the same storage, boundaries and grid
  * size in this process.  The tile shape changes only the speed, not the
  * results.  tile_out (host, may be NULL) receives the chosen index.  Without
- * a tuning call the library picks, for FP32 and 16-bit grids at least 256 x 64
- * nodes, 64 x 16 two-step tiles (7) when the two states fit 160 MB or the
- * storage is 16-bit and 64 x 8 two-step tiles (5) otherwise; for other grids
- * and FP64, 128 x 4 (2) when at least 256 nodes wide and 64 x 4 (0)
- * otherwise.  The environment variable PRC_TILE, read once, forces a shape
+ * a tuning call the library picks, for grids at least 256 x 64 nodes, a
+ * two-step shape: 64 x 16 (7) for FP32 when the two states fit 160 MB and for
+ * 16-bit storage, 64 x 8 (5) for larger FP32 states and for FP64 states that
+ * fit 160 MB, 32 x 16 (6) for larger FP64 states; for smaller grids 128 x 4
+ * (2) when at least 256 nodes wide and 64 x 4 (0) otherwise.  The environment variable PRC_TILE, read once, forces a shape
  * where it is allowed.  Synchronises the stream; PRC_EHIP if the scratch
  * allocation fails. */
 prc_status prc_tune(const prc_params *p, int32_t *tile_out, hipStream_t stream);
@@ -292,7 +292,7 @@ prc_status prc_batch_solve(prc_batch *b, double tol, int64_t check_every, int64_
 
 /* Autotuner for the batch sweep: time each tile shape a batch can use
  * (indices 0 .. 6 of prc_tune: the single-step shapes and the two-step 64 x 8
- * and 32 x 16; no two-step shape for FP64) on the current members, sweeping f_a into f_b (f_a, which holds
+ * and 32 x 16) on the current members, sweeping f_a into f_b (f_a, which holds
  * the state, is only read), and keep the fastest for this batch.  tile_out
  * (may be NULL) receives it.  Synchronises the stream. */
 prc_status prc_batch_tune(prc_batch *b, int32_t *tile_out, hipStream_t stream);

@@ -130,8 +130,8 @@ static int batch_tile(const prc_batch &b)
     if (b.tile >= 0) return b.tile;
     // measured on MI355X for batches of 64..512-wide cavities: 32 x 16 tiles
     // waste few threads at ragged edges, and two steps per launch halve the
-    // state traffic (no two-step shape for FP64)
-    return b.storage == PRC_F64 ? 4 : 6;
+    // state traffic
+    return 6;
 }
 
 static void drop_graph(prc_batch &b)
@@ -226,13 +226,9 @@ static prc_status launch_batch_shape(const prc_batch &b, int v, int parity, hipS
     const int nt = b.ntiles[v];
     const int per_xcd = (nt + kXcds - 1) / kXcds;
     if constexpr (STEPS == 2) {
-        if constexpr (sizeof(ST) <= 4)
-            hipLaunchKernelGGL((k_sweep_batch2<ST, BC, TX, TY, FORCE, ALL>),
-                               dim3(per_xcd * kXcds), dim3(TX * TY), 0, s,
-                               (const BatchTile *)b.d_tiles[v].ptr, nt, per_xcd,
-                               (const BatchMember<CT> *)b.d_members.ptr, parity);
-        else
-            return fail(PRC_EINVAL, "two-step sweep shapes need FP32 or 16-bit storage");
+        hipLaunchKernelGGL((k_sweep_batch2<ST, BC, TX, TY, FORCE, ALL>), dim3(per_xcd * kXcds),
+                           dim3(TX * TY), 0, s, (const BatchTile *)b.d_tiles[v].ptr, nt, per_xcd,
+                           (const BatchMember<CT> *)b.d_members.ptr, parity);
     } else {
         hipLaunchKernelGGL((k_sweep_batch<ST, BC, TX, TY, FORCE, ALL>), dim3(per_xcd * kXcds),
                            dim3(TX * TY), 0, s, (const BatchTile *)b.d_tiles[v].ptr, nt, per_xcd,
@@ -627,7 +623,6 @@ prc_status prc_batch_tune(prc_batch *b, int32_t *tile_out, hipStream_t stream)
     hipError_t he = hipEventCreate(&e0);
     if (he == hipSuccess) he = hipEventCreate(&e1);
     for (int t = 0; t < kNumBatchTiles && he == hipSuccess && st == PRC_OK; ++t) {
-        if (kTiles[t].steps == 2 && b->storage == PRC_F64) continue;
         b->tile = t;
         b->dirty = true;
         if ((st = ensure_tables(*b, stream)) != PRC_OK) break;
@@ -665,8 +660,6 @@ prc_status prc_batch_set_tile(prc_batch *b, int32_t tile)
     if (tile < 0 || tile >= kNumBatchTiles)
         return fail(PRC_EINVAL, "tile %d out of range for a batch (0 .. %d)", tile,
                     kNumBatchTiles - 1);
-    if (kTiles[tile].steps == 2 && b->storage == PRC_F64)
-        return fail(PRC_EINVAL, "tile %d (two steps per launch) needs FP32 or 16-bit storage", tile);
     if (tile != b->tile) {
         b->tile = tile;
         b->dirty = true;

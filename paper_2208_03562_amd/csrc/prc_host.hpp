@@ -188,10 +188,11 @@ constexpr int kNumSingleStepTiles = 5;  // indices below this advance one step
 // 32 x 16 -> 4), so that one tile list serves both.
 constexpr int kNumBatchTiles = 7;
 
-// Whether tile shape `tile` may run problem p (two-step shapes: no FP64).
+// Whether tile shape `tile` may run problem p (every shape runs every storage).
 inline bool tile_allowed(const prc_params &p, int tile)
 {
-    return tile >= 0 && tile < kNumTiles && (kTiles[tile].steps == 1 || p.storage != PRC_F64);
+    (void)p;
+    return tile >= 0 && tile < kNumTiles;
 }
 
 // run F<ST, BC>(args...) for the storage and boundary type of p

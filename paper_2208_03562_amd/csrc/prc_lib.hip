@@ -87,15 +87,17 @@ static int tile_choice(const prc_params &p)
         if (it != g_tuned.end()) return it->second;
     }
     // measured on MI355X: on grids that fill the chip two steps per launch
-    // pay for FP32 and 16-bit storage alike; 1024-thread tiles (64 x 16) are
-    // fastest while the two states stay in the last-level cache and for
-    // 16-bit storage, 512-thread tiles (64 x 8) for FP32 states streamed
-    // from HBM
-    if (p.storage != PRC_F64 && p.nx >= 256 && p.ny >= 64) {
+    // pay for every storage type.  FP32: 1024-thread tiles (64 x 16) while the
+    // two states stay in the last-level cache, 512-thread tiles (64 x 8) for
+    // states streamed from HBM; 16-bit: 64 x 16; FP64 (twice the LDS per
+    // tile): 64 x 8 in the cache, 32 x 16 from HBM
+    if (p.nx >= 256 && p.ny >= 64) {
         int64_t row, plane, total;
         layout(p, row, plane, total);
         const bool cached = 2 * total * (int64_t)elem_bytes(p.storage) <= kNtPairBytes;
-        return (cached || p.storage != PRC_F32) ? 7 : 5;
+        if (p.storage == PRC_F64) return cached ? 5 : 6;
+        if (p.storage == PRC_F32) return cached ? 7 : 5;
+        return 7;
     }
     return p.nx >= 256 ? 2 : 0;
 }
@@ -109,12 +111,8 @@ static prc_status launch_sweep_shape(const prc_params &p, const void *src, void 
     const int tiles = c.tiles_x * c.tiles_y;
     c.tiles_per_xcd = (tiles + kXcds - 1) / kXcds;
     if constexpr (STEPS == 2) {
-        if constexpr (sizeof(ST) <= 4)
-            hipLaunchKernelGGL((k_sweep2<ST, BC, TX, TY, FORCE, ALL>),
-                               dim3(c.tiles_per_xcd * kXcds), dim3(TX * TY), 0, s,
-                               (const ST *)src, (ST *)dst, c);
-        else
-            return fail(PRC_EINVAL, "two-step sweep shapes need FP32 or 16-bit storage");
+        hipLaunchKernelGGL((k_sweep2<ST, BC, TX, TY, FORCE, ALL>), dim3(c.tiles_per_xcd * kXcds),
+                           dim3(TX * TY), 0, s, (const ST *)src, (ST *)dst, c);
     } else {
         hipLaunchKernelGGL((k_sweep<ST, BC, TX, TY, FORCE, ALL>), dim3(c.tiles_per_xcd * kXcds),
                            dim3(TX * TY), 0, s, (const ST *)src, (ST *)dst, c);
@@ -517,9 +515,8 @@ prc_status prc_set_tile(const prc_params *p, int32_t tile)
 {
     prc_status st = validate(p);
     if (st != PRC_OK) return st;
-    if (tile < -1 || tile >= kNumTiles) return fail(PRC_EINVAL, "tile %d out of range", tile);
-    if (tile >= 0 && !tile_allowed(*p, tile))
-        return fail(PRC_EINVAL, "tile %d (two steps per launch) needs FP32 or 16-bit storage", tile);
+    if (tile < -1 || (tile >= 0 && !tile_allowed(*p, tile)))
+        return fail(PRC_EINVAL, "tile %d out of range", tile);
     std::lock_guard<std::mutex> lock(g_tune_mu);
     if (tile < 0)
         g_tuned.erase(tune_key(*p));

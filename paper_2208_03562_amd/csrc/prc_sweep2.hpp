@@ -32,6 +32,10 @@ namespace prc {
 // Population a of LDS-resident state: element type of the storage, so that
 // the intermediate step is rounded exactly as a stored state.
 template <typename ST> struct LdsVal;
+template <> struct LdsVal<double> {
+    static __device__ __forceinline__ double put(double x) { return x; }
+    static __device__ __forceinline__ double get(double x) { return x; }
+};
 template <> struct LdsVal<float> {
     static __device__ __forceinline__ float put(float x) { return x; }
     static __device__ __forceinline__ float get(float x) { return x; }
@@ -124,7 +128,6 @@ __device__ __forceinline__ void sweep2_tile(const Coef<typename Mem<ST>::CT> &c,
 {
     using CT = typename Mem<ST>::CT;
     using R = Regions2<TX, TY>;
-    static_assert(sizeof(ST) <= 4, "two-step sweep for FP32 and 16-bit storage");
     __shared__ CT D1[R::H3][R::W3];        // step-1 densities, origin (3, 3)
     __shared__ ST P1[9][R::H2][R::W2];     // step-1 post-collision state, origin (2, 2)
     __shared__ CT D2[TY + 2][TX + 2];      // step-2 densities, origin (1, 1)

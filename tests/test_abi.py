@@ -111,13 +111,15 @@ def test_from_re_rejects_bad_input():
 def test_set_tile_validates_without_gpu():
     p = base()
     capi.prc_set_tile(p, 1)
-    capi.prc_set_tile(p, 7)      # two steps per launch: FP32 and 16-bit storage
+    capi.prc_set_tile(p, 7)      # two steps per launch
     capi.prc_set_tile(p, -1)
     with pytest.raises(capi.PrcError):
         capi.prc_set_tile(p, 9)
-    p.storage = capi.PRC_F64
     with pytest.raises(capi.PrcError):
-        capi.prc_set_tile(p, 5)
+        capi.prc_set_tile(p, -2)
+    p.storage = capi.PRC_F64
+    capi.prc_set_tile(p, 5)      # every shape runs every storage
+    capi.prc_set_tile(p, -1)
 
 
 # ---- batches: host-side argument checks (nothing is launched) -------------
@@ -246,11 +248,12 @@ def test_tile_info():
         capi.prc_tile_info(9)
 
 
-def test_batch_two_step_shapes_refused_for_fp64():
+def test_batch_tile_range():
     b = capi.prc_batch_create(capi.PRC_F64, capi.PRC_BC_CAVITY)
     try:
-        with pytest.raises(capi.PrcError):
-            capi.prc_batch_set_tile(b, 5)
+        capi.prc_batch_set_tile(b, 5)    # two steps per launch, FP64 included
         capi.prc_batch_set_tile(b, 4)
+        with pytest.raises(capi.PrcError):
+            capi.prc_batch_set_tile(b, 7)  # not a batch shape
     finally:
         capi.prc_batch_destroy(b)

@@ -110,7 +110,7 @@ def test_member_joining_later_and_removal(torch_cuda):
 
 
 @pytest.mark.parametrize("storage,tile", [("f64", None), ("f16", None), ("bf16", None),
-                                          ("f16", 5), ("bf16", 6)])
+                                          ("f16", 5), ("bf16", 6), ("f64", 5), ("f64", 6)])
 def test_batch_other_storage_types(torch_cuda, storage, tile):
     from paper_2208_03562_amd import capi, solver
     specs = [dict(MIX[0], storage=storage), dict(MIX[1], storage=storage),

@@ -37,6 +37,27 @@ def test_4096x2048_one_step_every_node(O, storage):
     assert err < ONE_STEP_BOUND[storage], err
 
 
+def test_4096x2048_f64_two_step_launches_every_node(O):
+    """The full-size shallow cavity in FP64, four steps (two two-step
+    launches with the library's default shape for this size) from a seeded
+    random state, against the oracle at every node."""
+    w = workloads.CAVITY_4096x2048_MA002["f64"]
+    s = spec(w.nx, w.ny, w.r, w.gamma, re=w.re, omega_nu=None, u_lid=w.u_lid, storage="f64")
+    from paper_2208_03562_amd import capi, solver
+    sol = solver.Solver(lib_params(s))
+    noise = workloads.deviation_noise(w.nx, w.ny, seed=4097, amplitude=1e-3)
+    sol.set_state(noise)
+    po = oracle_params(O, s)
+    ft = np.ascontiguousarray(O.rest_state(po) + noise)
+    del noise
+    sol.step(4)
+    O.step(po, ft, 4)
+    dev = oracle_deviation(O, po, ft)
+    got = sol.get_state().cpu().numpy()
+    err = np.abs(got - dev).max() / np.abs(dev).max()
+    assert err < 1e-12, err
+
+
 def test_largest_state_corners_match_a_small_cavity(O):
     """The largest FP32 state (16384 x ny_max nodes, just under 4 GiB): after
     k steps from rest a node depends only on nodes within 2k of it (one link

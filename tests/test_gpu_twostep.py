@@ -1,7 +1,7 @@
 """Two time steps per launch (tile shapes 5-8): every node passes through
 exactly the single-step arithmetic, with the intermediate state rounded to
 the storage type, so the results must be the single-step sweep's bits -- for
-every boundary type, storage (FP32, FP16, BF16), sweep variant and frame, on
+every boundary type, storage (FP64, FP32, FP16, BF16), sweep variant and frame, on
 grids smaller than a tile and with ragged edges, over step counts that use
 the two-step launches alone, with single steps around them, and through the
 captured graphs."""
@@ -36,7 +36,7 @@ def run(s, tile, nsteps, seed):
     return out
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
 @pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}-r{c[1]}-g{c[2]}")
 @pytest.mark.parametrize("nx,ny", GRIDS)
 def test_two_step_launches_give_the_single_step_bits(storage, case, nx, ny):

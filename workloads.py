@@ -137,5 +137,5 @@ MA002_LID_R05 = 0.02 * 0.5 / math.sqrt(3.0)
 CAVITY_4096x2048_MA002 = {
     s: Cavity(f"cavity_4096x2048_r0.5_re2000_g0.05_ma0.02_{s}", 4096, 2048, 0.5, 2000.0,
               MA002_LID_R05, 0.05, s, check_every=1000, tol=1e-8, max_steps=10 ** 9)
-    for s in ("f32", "f16", "bf16")
+    for s in ("f64", "f32", "f16", "bf16")
 }
