@@ -176,9 +176,9 @@ struct TileShape {
 };
 // Narrow shapes waste fewer threads on grids whose width is not a multiple
 // of 64 (batches of small problems); a wavefront then spans two or four rows.
-// The two-step shapes (FP32 and 16-bit storage, single problems) trade the
-// collisions of two extra rings per tile for half the state traffic and half
-// the launches; squarer tiles have relatively smaller rings.
+// The two-step shapes (5 and 6 also for batches) trade the collisions of two
+// extra rings per tile for half the state traffic and half the launches;
+// squarer tiles have relatively smaller rings.
 constexpr TileShape kTiles[] = {{64, 4, 1},  {64, 8, 1},  {128, 4, 1}, {32, 8, 1}, {32, 16, 1},
                                 {64, 8, 2},  {32, 16, 2}, {64, 16, 2}, {32, 32, 2}};
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
