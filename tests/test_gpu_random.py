@@ -1,0 +1,64 @@
+"""GPU parity on seeded random problems: grid size, aspect ratio,
+preconditioning, relaxation rates, correction mask, frame, body force,
+boundary type, storage, tile shape and step count drawn from
+numpy.random.default_rng, each run against the FP64 oracle from the same
+rounded random state.  Bars as in test_gpu_parity: FP64 populations within
+1e-12 of the largest deviation per step, FP32 within 1e-5 of it per step."""
+import numpy as np
+import pytest
+
+import workloads
+from tests.common import lib_params, oracle_deviation, oracle_params, spec
+
+pytestmark = pytest.mark.gpu
+
+NP_STORAGE = {"f64": np.float64, "f32": np.float32}
+BOUND = {"f64": 1e-12, "f32": 1e-5}
+
+
+def draw(seed):
+    rng = np.random.default_rng(seed)
+    bc = ["cavity", "periodic", "channel"][rng.integers(3)]
+    r = float(rng.choice([0.25, 0.5, 0.8, 1.0, 1.6, 2.0, 4.0]))
+    q = min(1.0, r)
+    plain = rng.random() < 0.5       # the method as published, or a general setting
+    extra = dict(
+        nx=int(rng.integers(3, 140)), ny=int(rng.integers(3, 90)), r=r,
+        gamma=float(rng.uniform(0.1, 1.0)), omega_nu=float(rng.uniform(0.5, 1.8)),
+        bc=bc, storage=["f64", "f32"][rng.integers(2)],
+        u_lid=0.0 if bc == "periodic" else float(rng.uniform(0.0, 0.1) * q / np.sqrt(3.0)))
+    if not plain:
+        extra.update(
+            corrections=int(rng.integers(0, 8)), frame=int(rng.integers(2)),
+            omega_xi=float(rng.uniform(0.8, 1.5)), omega_1=float(rng.uniform(0.8, 1.5)),
+            omega_3=float(rng.uniform(0.8, 1.5)), omega_4=float(rng.uniform(0.8, 1.5)),
+            fx=float(rng.uniform(-1e-5, 1e-5)), fy=float(rng.uniform(-1e-5, 1e-5)))
+    tile = int(rng.integers(-1, 9))   # -1: the library's default
+    nsteps = int(rng.integers(1, 10))
+    return extra, tile, nsteps
+
+
+@pytest.mark.parametrize("seed", range(120))
+def test_random_problem_against_oracle(O, seed):
+    from paper_2208_03562_amd import capi, solver
+    extra, tile, nsteps = draw(seed)
+    nx, ny = extra.pop("nx"), extra.pop("ny")
+    s = spec(nx, ny, **extra)
+    p = lib_params(s)
+    if tile >= 0:
+        capi.prc_set_tile(p, tile)
+    try:
+        sol = solver.Solver(p)
+        noise = workloads.deviation_noise(nx, ny, 1000 + seed, 1e-3)
+        noise = noise.astype(NP_STORAGE[s["storage"]]).astype(np.float64)
+        sol.set_state(noise)
+        po = oracle_params(O, s)
+        ft = np.ascontiguousarray(O.rest_state(po) + noise)
+        sol.step(nsteps)
+        O.step(po, ft, nsteps)
+        dev = oracle_deviation(O, po, ft)
+        got = sol.get_state().cpu().numpy()
+    finally:
+        capi.prc_set_tile(p, -1)
+    err = np.abs(got - dev).max() / np.abs(dev).max()
+    assert err < BOUND[s["storage"]] * nsteps, (s, tile, nsteps, err)
