@@ -2,8 +2,9 @@
 preconditioning, relaxation rates, correction mask, frame, body force,
 boundary type, storage, tile shape and step count drawn from
 numpy.random.default_rng, each run against the FP64 oracle from the same
-rounded random state.  Bars as in test_gpu_parity: FP64 populations within
-1e-12 of the largest deviation per step, FP32 within 1e-5 of it per step."""
+rounded random state.  Bars per step, relative to the largest deviation, as
+in test_gpu_parity and test_gpu_precision: FP64 1e-12, FP32 1e-5, FP16 2e-3,
+BF16 1.6e-2."""
 import numpy as np
 import pytest
 
@@ -12,8 +13,15 @@ from tests.common import lib_params, oracle_deviation, oracle_params, spec
 
 pytestmark = pytest.mark.gpu
 
-NP_STORAGE = {"f64": np.float64, "f32": np.float32}
-BOUND = {"f64": 1e-12, "f32": 1e-5}
+BOUND = {"f64": 1e-12, "f32": 1e-5, "f16": 2e-3, "bf16": 1.6e-2}
+
+
+def rounded(a, storage):
+    """a rounded to the storage type and back (the state both sides start from)"""
+    import torch
+    dt = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float16,
+          "bf16": torch.bfloat16}[storage]
+    return torch.from_numpy(a).to(dt).double().numpy()
 
 
 def draw(seed):
@@ -25,7 +33,7 @@ def draw(seed):
     extra = dict(
         nx=int(rng.integers(3, 140)), ny=int(rng.integers(3, 90)), r=r,
         gamma=float(rng.uniform(0.1, 1.0)), omega_nu=float(rng.uniform(0.5, 1.8)),
-        bc=bc, storage=["f64", "f32"][rng.integers(2)],
+        bc=bc, storage=["f64", "f32", "f16", "bf16"][rng.integers(4)],
         u_lid=0.0 if bc == "periodic" else float(rng.uniform(0.0, 0.1) * q / np.sqrt(3.0)))
     if not plain:
         extra.update(
@@ -50,7 +58,7 @@ def test_random_problem_against_oracle(O, seed):
     try:
         sol = solver.Solver(p)
         noise = workloads.deviation_noise(nx, ny, 1000 + seed, 1e-3)
-        noise = noise.astype(NP_STORAGE[s["storage"]]).astype(np.float64)
+        noise = rounded(noise, s["storage"])
         sol.set_state(noise)
         po = oracle_params(O, s)
         ft = np.ascontiguousarray(O.rest_state(po) + noise)
