@@ -265,9 +265,25 @@ __device__ __forceinline__ void sweep2_tile(const Coef<typename Mem<ST>::CT> &c,
     tile_finish<ST, TX, TY, FORCE, ALL>(c, make_rsrc(dst, c.state_bytes), D2, g, x0, y0, d);
 }
 
+// Waves per SIMD that the LDS of sweep2_tile leaves room for (160 KB per CU,
+// four SIMDs, at most eight waves each considered): the kernels ask the
+// compiler to fit their registers to it, so that the general variant, whose
+// collision needs a few more registers, keeps the occupancy the LDS allows.
+template <typename ST, int TX, int TY>
+constexpr int two_step_waves_per_simd()
+{
+    using CT = typename Mem<ST>::CT;
+    using R = Regions2<TX, TY>;
+    constexpr int lds = int(sizeof(CT)) * R::H3 * R::W3 + int(sizeof(ST)) * 9 * R::H2 * R::W2 +
+                        int(sizeof(CT)) * (TY + 2) * (TX + 2);
+    constexpr int w = (163840 / lds) * (R::T / 64) / 4;
+    return w < 1 ? 1 : (w > 8 ? 8 : w);
+}
+
 // One problem, one tile per workgroup, XCD-aware order as k_sweep.
 template <typename ST, int BC, int TX, int TY, bool FORCE, bool ALL>
 __global__ void __launch_bounds__(TX *TY)
+    __attribute__((amdgpu_waves_per_eu(two_step_waves_per_simd<ST, TX, TY>())))
     k_sweep2(const ST *__restrict__ src, ST *__restrict__ dst, const Coef<typename Mem<ST>::CT> c)
 {
     const int tile = (blockIdx.x % kXcds) * c.tiles_per_xcd + blockIdx.x / kXcds;
@@ -280,6 +296,7 @@ __global__ void __launch_bounds__(TX *TY)
 // buf[parity] into buf[parity ^ 1].
 template <typename ST, int BC, int TX, int TY, bool FORCE, bool ALL>
 __global__ void __launch_bounds__(TX *TY)
+    __attribute__((amdgpu_waves_per_eu(two_step_waves_per_simd<ST, TX, TY>())))
     k_sweep_batch2(const BatchTile *__restrict__ tiles, int ntiles, int tiles_per_xcd,
                    const BatchMember<typename Mem<ST>::CT> *__restrict__ members, int parity)
 {
