@@ -1,0 +1,51 @@
+// Launch of one sweep (one or two time steps) on a tile shape, shared by the
+// library's source files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "prc.h"
+#include "prc_coef.hpp"
+#include "prc_host.hpp"
+#include "prc_sweep.hpp"
+#include "prc_sweep2.hpp"
+
+namespace prc {
+
+template <typename ST, int BC, int TX, int TY, bool FORCE, bool ALL, int STEPS>
+inline prc_status launch_sweep_shape(const prc_params &p, const void *src, void *dst, hipStream_t s)
+{
+    auto c = coef_of<ST>(p);
+    c.tiles_x = (p.nx + TX - 1) / TX;
+    c.tiles_y = (p.ny + TY - 1) / TY;
+    const int tiles = c.tiles_x * c.tiles_y;
+    c.tiles_per_xcd = (tiles + kXcds - 1) / kXcds;
+    if constexpr (STEPS == 2) {
+        hipLaunchKernelGGL((k_sweep2<ST, BC, TX, TY, FORCE, ALL>), dim3(c.tiles_per_xcd * kXcds),
+                           dim3(TX * TY), 0, s, (const ST *)src, (ST *)dst, c);
+    } else {
+        hipLaunchKernelGGL((k_sweep<ST, BC, TX, TY, FORCE, ALL>), dim3(c.tiles_per_xcd * kXcds),
+                           dim3(TX * TY), 0, s, (const ST *)src, (ST *)dst, c);
+    }
+    HIP_TRY(hipGetLastError());
+    return PRC_OK;
+}
+
+// The method as the paper runs it (every correction, no body force, central
+// frame, unit non-hydrodynamic rates) runs a specialised kernel; anything
+// else runs the general one.
+template <typename ST, int BC, int TX, int TY, int STEPS = 1>
+inline prc_status launch_sweep_variant(const prc_params &p, const void *src, void *dst,
+                                       hipStream_t s)
+{
+    if (is_plain_method(p))
+        return launch_sweep_shape<ST, BC, TX, TY, false, true, STEPS>(p, src, dst, s);
+    return launch_sweep_shape<ST, BC, TX, TY, true, false, STEPS>(p, src, dst, s);
+}
+
+// One two-step launch on the 1024-thread tile shapes 7 (64 x 16) and 8
+// (32 x 32), defined in prc_wide.hip.
+prc_status launch_sweep_wide(const prc_params &p, int tile, const void *src, void *dst,
+                             hipStream_t s);
+
+}  // namespace prc

@@ -4,6 +4,8 @@
 //   k_sweep     one fused time step: pull with boundaries, fields, density
 //               gradient from an LDS tile of densities, collision, store
 //               (prc_sweep.hpp, prc_collide.hpp)
+//   k_sweep2    two time steps per launch (prc_sweep2.hpp); the 1024-thread
+//               tile shapes are launched from prc_wide.hip
 //   k_macros    fields of a state (for output)
 //   k_residual  per-block FP64 partial sums of the convergence check
 //   k_finish    fixed-order reduction of the partial sums (prc_reduce.hpp)
@@ -27,6 +29,7 @@
 #include "prc_coef.hpp"
 #include "prc_device.hpp"
 #include "prc_host.hpp"
+#include "prc_launch.hpp"
 #include "prc_reduce.hpp"
 #include "prc_sweep.hpp"
 #include "prc_sweep2.hpp"
@@ -102,37 +105,6 @@ static int tile_choice(const prc_params &p)
     return p.nx >= 256 ? 2 : 0;
 }
 
-template <typename ST, int BC, int TX, int TY, bool FORCE, bool ALL, int STEPS>
-static prc_status launch_sweep_shape(const prc_params &p, const void *src, void *dst, hipStream_t s)
-{
-    auto c = coef_of<ST>(p);
-    c.tiles_x = (p.nx + TX - 1) / TX;
-    c.tiles_y = (p.ny + TY - 1) / TY;
-    const int tiles = c.tiles_x * c.tiles_y;
-    c.tiles_per_xcd = (tiles + kXcds - 1) / kXcds;
-    if constexpr (STEPS == 2) {
-        hipLaunchKernelGGL((k_sweep2<ST, BC, TX, TY, FORCE, ALL>), dim3(c.tiles_per_xcd * kXcds),
-                           dim3(TX * TY), 0, s, (const ST *)src, (ST *)dst, c);
-    } else {
-        hipLaunchKernelGGL((k_sweep<ST, BC, TX, TY, FORCE, ALL>), dim3(c.tiles_per_xcd * kXcds),
-                           dim3(TX * TY), 0, s, (const ST *)src, (ST *)dst, c);
-    }
-    HIP_TRY(hipGetLastError());
-    return PRC_OK;
-}
-
-// The method as the paper runs it (every correction, no body force, central
-// frame, unit non-hydrodynamic rates) runs a specialised kernel; anything
-// else runs the general one.
-template <typename ST, int BC, int TX, int TY, int STEPS = 1>
-static prc_status launch_sweep_variant(const prc_params &p, const void *src, void *dst,
-                                       hipStream_t s)
-{
-    if (is_plain_method(p))
-        return launch_sweep_shape<ST, BC, TX, TY, false, true, STEPS>(p, src, dst, s);
-    return launch_sweep_shape<ST, BC, TX, TY, true, false, STEPS>(p, src, dst, s);
-}
-
 // One launch of tile shape `tile`: kTiles[tile].steps time steps, src -> dst.
 template <typename ST, int BC>
 static prc_status launch_sweep_tile(const prc_params &p, int tile, const void *src, void *dst,
@@ -145,8 +117,8 @@ static prc_status launch_sweep_tile(const prc_params &p, int tile, const void *s
     case 4: return launch_sweep_variant<ST, BC, 32, 16>(p, src, dst, s);
     case 5: return launch_sweep_variant<ST, BC, 64, 8, 2>(p, src, dst, s);
     case 6: return launch_sweep_variant<ST, BC, 32, 16, 2>(p, src, dst, s);
-    case 7: return launch_sweep_variant<ST, BC, 64, 16, 2>(p, src, dst, s);
-    case 8: return launch_sweep_variant<ST, BC, 32, 32, 2>(p, src, dst, s);
+    case 7:
+    case 8: return launch_sweep_wide(p, tile, src, dst, s);  // prc_wide.hip
     default: return launch_sweep_variant<ST, BC, 64, 4>(p, src, dst, s);
     }
 }
