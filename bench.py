@@ -346,14 +346,18 @@ def traffic_from_counters(pmc_dir: str):
     print(json.dumps(rec))
 
 
-def sweep_kernel_name(storage: str, bc: int, tile: int) -> str:
+def sweep_kernel_name(storage: str, bc: int, tile: int, state_bytes: int) -> str:
     """Demangled name of the sweep instance bench.py runs (the method as the
-    paper runs it) for a storage type, boundary type and tile index."""
+    paper runs it) for a storage type, boundary type, tile index and state
+    size (1024-thread two-step tiles have an instance for states streamed
+    from HBM, those whose two buffers exceed 160 MB)."""
     from paper_2208_03562_amd import capi
     tx, ty, steps = capi.prc_tile_info(tile)
     ctype = {"f64": "double", "f32": "float", "f16": "__half", "bf16": "__hip_bfloat16"}[storage]
-    kern = "k_sweep2" if steps == 2 else "k_sweep"
-    return f"prc::{kern}<{ctype}, {bc}, {tx}, {ty}, false, true>"
+    if steps == 1:
+        return f"prc::k_sweep<{ctype}, {bc}, {tx}, {ty}, false, true>"
+    streamed = tx * ty > 512 and 2 * state_bytes > 160 * 2 ** 20
+    return f"prc::k_sweep2<{ctype}, {bc}, {tx}, {ty}, false, true, {str(streamed).lower()}>"
 
 
 def trace_summary(trace_dir: str):
@@ -456,7 +460,10 @@ def main():
     parity = oracle_parity(w, wc) if args.cpu_budget > 0 else None
     cpu = run_cpu_baseline(w, args.cpu_budget) if args.cpu_budget > 0 else None
     _, _, per_launch = capi.prc_tile_info(main_res["tile"])
-    kernel = sweep_kernel_name(w.storage, 0, main_res["tile"])
+    from paper_2208_03562_amd import solver as _solver
+    state_bytes = capi.prc_state_bytes(_solver.make_params(
+        w.nx, w.ny, w.r, w.gamma, re=w.re, u_lid=w.u_lid, storage=STORAGE[w.storage]))
+    kernel = sweep_kernel_name(w.storage, 0, main_res["tile"], state_bytes)
     traffic = measured_traffic(w, kernel)
     nodes = w.nx * w.ny
 

@@ -188,9 +188,9 @@ prc_status prc_solve(const prc_params *p, void *f_a, void *f_b, double *u_prev,
  * results.  tile_out (host, may be NULL) receives the chosen index.  Without
  * a tuning call the library picks, for grids at least 256 x 64 nodes, a
  * two-step shape: 64 x 16 (7) for FP32 when the two states fit 160 MB and for
- * 16-bit storage, 64 x 8 (5) for larger FP32 states and for FP64 states that
- * fit 160 MB, 32 x 16 (6) for larger FP64 states; for smaller grids 128 x 4
- * (2) when at least 256 nodes wide and 64 x 4 (0) otherwise.  The environment variable PRC_TILE, read once, forces a shape
+ * 16-bit storage, 32 x 32 (8) for larger FP32 states, 64 x 8 (5) for FP64
+ * states that fit 160 MB and 32 x 16 (6) for larger ones; for smaller grids
+ * 128 x 4 (2) when at least 256 nodes wide and 64 x 4 (0) otherwise.  The environment variable PRC_TILE, read once, forces a shape
  * where it is allowed.  Synchronises the stream; PRC_EHIP if the scratch
  * allocation fails. */
 prc_status prc_tune(const prc_params *p, int32_t *tile_out, hipStream_t stream);

@@ -21,8 +21,22 @@ inline prc_status launch_sweep_shape(const prc_params &p, const void *src, void 
     const int tiles = c.tiles_x * c.tiles_y;
     c.tiles_per_xcd = (tiles + kXcds - 1) / kXcds;
     if constexpr (STEPS == 2) {
-        hipLaunchKernelGGL((k_sweep2<ST, BC, TX, TY, FORCE, ALL>), dim3(c.tiles_per_xcd * kXcds),
-                           dim3(TX * TY), 0, s, (const ST *)src, (ST *)dst, c);
+        // the load order differs for 1024-thread tiles of a state streamed
+        // from HBM (non-temporal stores mark it)
+        if constexpr (TX * TY > 512) {
+            if (c.nt)
+                hipLaunchKernelGGL((k_sweep2<ST, BC, TX, TY, FORCE, ALL, true>),
+                                   dim3(c.tiles_per_xcd * kXcds), dim3(TX * TY), 0, s,
+                                   (const ST *)src, (ST *)dst, c);
+            else
+                hipLaunchKernelGGL((k_sweep2<ST, BC, TX, TY, FORCE, ALL, false>),
+                                   dim3(c.tiles_per_xcd * kXcds), dim3(TX * TY), 0, s,
+                                   (const ST *)src, (ST *)dst, c);
+        } else {
+            hipLaunchKernelGGL((k_sweep2<ST, BC, TX, TY, FORCE, ALL, false>),
+                               dim3(c.tiles_per_xcd * kXcds), dim3(TX * TY), 0, s,
+                               (const ST *)src, (ST *)dst, c);
+        }
     } else {
         hipLaunchKernelGGL((k_sweep<ST, BC, TX, TY, FORCE, ALL>), dim3(c.tiles_per_xcd * kXcds),
                            dim3(TX * TY), 0, s, (const ST *)src, (ST *)dst, c);

@@ -90,16 +90,16 @@ static int tile_choice(const prc_params &p)
         if (it != g_tuned.end()) return it->second;
     }
     // measured on MI355X: on grids that fill the chip two steps per launch
-    // pay for every storage type.  FP32: 1024-thread tiles (64 x 16) while the
-    // two states stay in the last-level cache, 512-thread tiles (64 x 8) for
-    // states streamed from HBM; 16-bit: 64 x 16; FP64 (twice the LDS per
-    // tile): 64 x 8 in the cache, 32 x 16 from HBM
+    // pay for every storage type.  FP32: 64 x 16 tiles while the two states
+    // stay in the last-level cache, 32 x 32 for states streamed from HBM;
+    // 16-bit: 64 x 16; FP64 (twice the LDS per tile, so 512-thread tiles):
+    // 64 x 8 in the cache, 32 x 16 from HBM
     if (p.nx >= 256 && p.ny >= 64) {
         int64_t row, plane, total;
         layout(p, row, plane, total);
         const bool cached = 2 * total * (int64_t)elem_bytes(p.storage) <= kNtPairBytes;
         if (p.storage == PRC_F64) return cached ? 5 : 6;
-        if (p.storage == PRC_F32) return cached ? 7 : 5;
+        if (p.storage == PRC_F32) return cached ? 7 : 8;
         return 7;
     }
     return p.nx >= 256 ? 2 : 0;

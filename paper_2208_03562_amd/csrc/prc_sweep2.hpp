@@ -121,8 +121,10 @@ __device__ __forceinline__ void slot_node(const int nx, const int ny, int x0, in
 }
 
 // Two steps for the tile at (x0, y0) of one problem: src (state at step n) ->
-// dst (state at step n + 2).  Called by the whole workgroup.
-template <typename ST, int BC, int TX, int TY, bool FORCE, bool ALL>
+// dst (state at step n + 2).  Called by the whole workgroup.  STREAMED: the
+// state is streamed from HBM (it does not stay in the last-level cache from
+// one launch to the next), which changes only the order of the first loads.
+template <typename ST, int BC, int TX, int TY, bool FORCE, bool ALL, bool STREAMED>
 __device__ __forceinline__ void sweep2_tile(const Coef<typename Mem<ST>::CT> &c,
                                             const void *src, void *dst, int x0, int y0)
 {
@@ -156,13 +158,21 @@ __device__ __forceinline__ void sweep2_tile(const Coef<typename Mem<ST>::CT> &c,
     };
 
     // step 1: streaming and densities over R3; the R2 populations are kept
-    // for the collision.  Workgroups of up to 512 threads issue every load of
-    // the region before the first use; 1024-thread workgroups load the ring
-    // only after the densities of R2, which measured faster for them (and
-    // slower for the smaller ones) on cache-resident and HBM grids alike.
-    constexpr bool kEager = R::T <= 512;
+    // for the collision.  Workgroups of up to 512 threads, and every
+    // workgroup of a state streamed from HBM, issue every load of the region
+    // before the first use; 1024-thread workgroups over a state in the
+    // last-level cache load the ring only after the densities of R2, which
+    // measured faster for them there (and slower in the other cases).  The
+    // streamed instance keeps both orders behind the run-time flag c.nt
+    // (set for such states): compiled that way it measured 5 % faster than
+    // with the eager order alone (4096 x 2048 FP32 on 32 x 32 tiles: 72.9
+    // against 79.2 us per step), a difference in instruction scheduling only.
     CT keep[R::S2][9];
-    if constexpr (kEager) {
+    bool eager;
+    if constexpr (R::T <= 512) eager = true;
+    else if constexpr (STREAMED) eager = c.nt;
+    else eager = false;
+    if (eager) {
         CT ring[R::SB][9];
 #pragma unroll
         for (int s = 0; s < R::SB; ++s) {
@@ -281,7 +291,7 @@ constexpr int two_step_waves_per_simd()
 }
 
 // One problem, one tile per workgroup, XCD-aware order as k_sweep.
-template <typename ST, int BC, int TX, int TY, bool FORCE, bool ALL>
+template <typename ST, int BC, int TX, int TY, bool FORCE, bool ALL, bool STREAMED>
 __global__ void __launch_bounds__(TX *TY)
     __attribute__((amdgpu_waves_per_eu(two_step_waves_per_simd<ST, TX, TY>())))
     k_sweep2(const ST *__restrict__ src, ST *__restrict__ dst, const Coef<typename Mem<ST>::CT> c)
@@ -289,7 +299,7 @@ __global__ void __launch_bounds__(TX *TY)
     const int tile = (blockIdx.x % kXcds) * c.tiles_per_xcd + blockIdx.x / kXcds;
     if (tile >= c.tiles_x * c.tiles_y) return;
     const int x0 = (tile % c.tiles_x) * TX, y0 = (tile / c.tiles_x) * TY;
-    sweep2_tile<ST, BC, TX, TY, FORCE, ALL>(c, src, dst, x0, y0);
+    sweep2_tile<ST, BC, TX, TY, FORCE, ALL, STREAMED>(c, src, dst, x0, y0);
 }
 
 // A tile list over many problems (batches), as k_sweep_batch: two steps from
@@ -304,7 +314,7 @@ __global__ void __launch_bounds__(TX *TY)
     if (t >= ntiles) return;
     const BatchTile tl = tiles[t];
     const BatchMember<typename Mem<ST>::CT> &m = members[tl.member];
-    sweep2_tile<ST, BC, TX, TY, FORCE, ALL>(m.c, m.buf[parity], const_cast<void *>(m.buf[parity ^ 1]),
+    sweep2_tile<ST, BC, TX, TY, FORCE, ALL, false>(m.c, m.buf[parity], const_cast<void *>(m.buf[parity ^ 1]),
                                             tl.x0, tl.y0);
 }
 
