@@ -346,14 +346,26 @@ def traffic_from_counters(pmc_dir: str):
     print(json.dumps(rec))
 
 
+def steps_per_launch(tile: int) -> int:
+    """Time steps per sweep launch in the timed loop: the tile's own count, or
+    for the resident sweep (0: any count) one launch per call of CHECK_EVERY
+    steps."""
+    from paper_2208_03562_amd import capi
+    steps = capi.prc_tile_info(tile)[2]
+    return steps if steps > 0 else CHECK_EVERY
+
+
 def sweep_kernel_name(storage: str, bc: int, tile: int, state_bytes: int) -> str:
     """Demangled name of the sweep instance bench.py runs (the method as the
     paper runs it) for a storage type, boundary type, tile index and state
     size (1024-thread two-step tiles have an instance for states streamed
-    from HBM, those whose two buffers exceed 160 MB)."""
+    from HBM, those whose two buffers exceed 160 MB; tile 9 is the resident
+    sweep)."""
     from paper_2208_03562_amd import capi
     tx, ty, steps = capi.prc_tile_info(tile)
     ctype = {"f64": "double", "f32": "float", "f16": "__half", "bf16": "__hip_bfloat16"}[storage]
+    if steps == 0:
+        return f"prc::k_resident<{ctype}, {bc}, false, true>"
     if steps == 1:
         return f"prc::k_sweep<{ctype}, {bc}, {tx}, {ty}, false, true>"
     streamed = tx * ty > 512 and 2 * state_bytes > 160 * 2 ** 20
@@ -450,7 +462,7 @@ def main():
             big[wh.name] = dict(
                 workload=wh.name, u_lid=round(wh.u_lid, 6), mlups=round(r["mlups"], 1),
                 sweep_us=round(r["sweep_us"], 2), achieved_gbs=round(r["sweep_gbs"], 1),
-                tile=r["tile"], steps_per_launch=capi.prc_tile_info(r["tile"])[2],
+                tile=r["tile"], steps_per_launch=steps_per_launch(r["tile"]),
                 frac=round(r["sweep_gbs"] / HBM_PEAK_GBS, 4),
                 bytes_per_node=BYTES_PER_NODE[wh.storage], diverged_at_step=r["diverged_at"])
     batch = run_batch(args.batch_instances, 16) if args.batch_instances > 0 else None
@@ -459,7 +471,7 @@ def main():
              if args.serve_requests > 0 else None)
     parity = oracle_parity(w, wc) if args.cpu_budget > 0 else None
     cpu = run_cpu_baseline(w, args.cpu_budget) if args.cpu_budget > 0 else None
-    _, _, per_launch = capi.prc_tile_info(main_res["tile"])
+    per_launch = steps_per_launch(main_res["tile"])
     from paper_2208_03562_amd import solver as _solver
     state_bytes = capi.prc_state_bytes(_solver.make_params(
         w.nx, w.ny, w.r, w.gamma, re=w.re, u_lid=w.u_lid, storage=STORAGE[w.storage]))
@@ -493,9 +505,11 @@ def main():
                      "kernel_us": round(main_res["sweep_us"] * per_launch, 3),
                      "note": f"72 B per node update (9 FP32 reads + 9 FP32 writes) x {nodes} "
                              f"nodes x {per_launch} step(s) per launch; achieved = those bytes / "
-                             "launch time.  A two-step launch keeps the intermediate state in "
-                             "LDS, so it moves fewer bytes than that (traffic); the 37.7 MB "
-                             "state stays in the last-level cache"},
+                             "launch time.  The resident sweep keeps the state in LDS for all "
+                             "the steps of a launch and moves only the subdomains' edges "
+                             "between steps (traffic); a two-step launch keeps the intermediate "
+                             "state in LDS.  Either moves fewer bytes than the algorithmic "
+                             "count"},
         "solution": {"diverged_at_step": main_res["diverged_at"],
                      "residual_last": main_res["residual_last"],
                      "note": "U = 0.05 with gamma = 0.1 is outside the scheme's stable range; "

@@ -17,8 +17,11 @@
  *  - All state buffers are device memory allocated and owned by the caller;
  *    the single-problem calls keep no pointer after they return and allocate
  *    no device memory of their own, except the cached launch graphs of
- *    prc_step (until prc_release_graphs or process exit) and the scratch
- *    states prc_tune allocates and frees within the call.  A batch owns its
+ *    prc_step (until prc_release_graphs or process exit), the scratch
+ *    states prc_tune allocates and frees within the call, and, on a device
+ *    where the resident sweep (tile 9) runs, its counters and exchange
+ *    buffer (about 28 MB, allocated and cleared once, kept until process
+ *    exit).  A batch owns its
  *    small tables and graphs until prc_batch_destroy; prc_serve allocates its
  *    request pool for the duration of the call.
  *  - Calls are ordered on the HIP stream passed in (0 = null stream) and are
@@ -138,7 +141,9 @@ prc_status prc_init(const prc_params *p, void *f, hipStream_t stream);
 /* Advance nsteps >= 0 time steps of Appendix A.  Each step reads one state
  * buffer and writes the other: step k (k = 0, 1, ...) reads f_a when k is
  * even and f_b when k is odd, so after nsteps steps the newest state is in
- * f_a when nsteps is even and in f_b when it is odd.  One step = streaming
+ * f_a when nsteps is even and in f_b when it is odd (the other buffer holds
+ * an earlier state; the resident sweep, which keeps the state in LDS between
+ * steps, may leave it as it was).  One step = streaming
  * with boundaries (Appendix A, "stream"; moving-wall bounce-back as noted at
  * the end of Appendix A), the hydrodynamic fields of the streamed state
  * (eq. hydrodynamicfields), the density gradient, and the collision.  f_a and
@@ -153,7 +158,10 @@ prc_status prc_step(const prc_params *p, void *f_a, void *f_b, int64_t nsteps,
  * then overwrites u_prev with u.  The relative residual is
  * sqrt(out[0] / out[1]).  u_prev: device double[2][ny][nx] (u_x plane, then
  * u_y plane); scratch: device, prc_scratch_bytes; out: host double[4].
- * Synchronises the stream.  The sums are reproduced bit for bit run to run. */
+ * Synchronises the stream.  The sums are reproduced bit for bit run to run.
+ * Returns PRC_EHIP (and clears the report) if a resident sweep on this device
+ * gave up waiting for a neighbouring subdomain since the last check (every
+ * subdomain must have a compute unit at once; the state is then invalid). */
 prc_status prc_residual(const prc_params *p, const void *f, double *u_prev,
                         void *scratch, double out[4], hipStream_t stream);
 
@@ -179,14 +187,19 @@ prc_status prc_solve(const prc_params *p, void *f_a, void *f_b, double *u_prev,
 /* Autotuner: time every tile shape of the sweep kernel (threads along x by
  * along y: 0 = 64 x 4, 1 = 64 x 8, 2 = 128 x 4, 3 = 32 x 8, 4 = 32 x 16, one
  * time step per launch; 5 = 64 x 8, 6 = 32 x 16, 7 = 64 x 16, 8 = 32 x 32, two
- * time steps per launch with the intermediate state in LDS; see
- * prc_tile_info) for this problem's storage,
+ * time steps per launch with the intermediate state in LDS; 9 = the resident
+ * sweep, 64 x 32-node subdomains of 1024 threads, one per compute unit, that
+ * keep the state in LDS for all the steps of a prc_step call and exchange
+ * only their edges through memory -- FP32 and 16-bit storage on grids of at
+ * most one subdomain per compute unit, a periodic side a multiple of the
+ * subdomain; see prc_tile_info) for this problem's storage,
  * boundaries and grid size, on two scratch state buffers that the call
  * allocates and frees itself (hipMalloc/hipFree), and use the fastest (per time step) for
  * every later sweep of a problem with the same storage, boundaries and grid
  * size in this process.  The tile shape changes only the speed, not the
  * results.  tile_out (host, may be NULL) receives the chosen index.  Without
- * a tuning call the library picks, for grids at least 256 x 64 nodes, a
+ * a tuning call the library picks, for grids at least 256 x 64 nodes, the
+ * resident sweep (9) where it can run the problem, else a
  * two-step shape: 64 x 16 (7) for FP32 when the two states fit 160 MB and for
  * 16-bit storage, 32 x 32 (8) for larger FP32 states, 64 x 8 (5) for FP64
  * states that fit 160 MB and 32 x 16 (6) for larger ones; for smaller grids
@@ -195,17 +208,21 @@ prc_status prc_solve(const prc_params *p, void *f_a, void *f_b, double *u_prev,
  * allocation fails. */
 prc_status prc_tune(const prc_params *p, int32_t *tile_out, hipStream_t stream);
 
-/* Shape of tile index `tile` (0 .. 8): threads along x and y and time steps
- * per launch.  A two-step launch computes the intermediate step on the tile
- * plus two rings in LDS (temporal blocking, for states that fit the cache or
- * to halve the state traffic); its results are bit for bit those of two
- * single steps.  Any output pointer may be NULL.  Host only. */
+/* Shape of tile index `tile` (0 .. 9): threads along x and y (for the
+ * resident sweep, 9: nodes of a subdomain) and time steps per launch (0 for
+ * the resident sweep: any number).  A two-step launch computes the
+ * intermediate step on the tile plus two rings in LDS (temporal blocking, for
+ * states that fit the cache or to halve the state traffic); its results, and
+ * the resident sweep's, are bit for bit those of single steps.  Any output
+ * pointer may be NULL.  Host only. */
 prc_status prc_tile_info(int32_t tile, int32_t *tx, int32_t *ty, int32_t *steps);
 
 /* Use tile shape `tile` (index as for prc_tune; -1 forgets any choice) for
- * problems with this storage, boundaries and grid size.  Host only; does not
- * touch the GPU.  Launch graphs already cached by prc_step keep the shape
- * they were captured with until prc_release_graphs. */
+ * problems with this storage, boundaries and grid size.  Host only; launches
+ * nothing (for the resident sweep it reads the current device's compute
+ * units and LDS size, and fails without a device or where the problem does
+ * not fit).  Launch graphs already cached by prc_step keep the shape they
+ * were captured with until prc_release_graphs. */
 prc_status prc_set_tile(const prc_params *p, int32_t tile);
 
 /* Drop the launch graphs cached by prc_step (they hold no user memory). */

@@ -8,12 +8,14 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libprc.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("prc_lib.hip", "prc_batch.hip", "prc_serve.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("prc_lib.hip", "prc_batch.hip", "prc_serve.hip",
+                                              "prc_resident.hip")]
 # compiled on its own with WIDE_FLAGS added: the two-step sweep on 1024-thread tiles
 WIDE = os.path.join(CSRC, "prc_wide.hip")
 HEADERS = [os.path.join(CSRC, h) for h in ("prc_coef.hpp", "prc_device.hpp", "prc_collide.hpp",
                                          "prc_sweep.hpp", "prc_host.hpp", "prc_reduce.hpp",
-                                         "prc_batch.hpp", "prc_sweep2.hpp", "prc_launch.hpp")] + [
+                                         "prc_batch.hpp", "prc_sweep2.hpp", "prc_launch.hpp",
+                                         "prc_resident.hpp")] + [
     os.path.join(ROOT, "include", "prc.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

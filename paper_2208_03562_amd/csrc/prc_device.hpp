@@ -48,6 +48,18 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint32_t bytes)
                                              kRsrcWord3);
 }
 
+// x as computed, for a conversion to a 16-bit type: the empty register
+// constraint keeps the compiler from fusing the conversion into the
+// multiply-add that produced x (one rounding of the exact result to 16 bits,
+// v_fma_mixlo_f16), which it does or not depending on the shape of the code
+// around it; so every kernel rounds twice, to float and then to 16 bits, as
+// the source says, and kernels of different shape give the same bits.
+__device__ __forceinline__ float as_computed(float x)
+{
+    asm("" : "+v"(x));
+    return x;
+}
+
 template <typename ST> struct Mem;
 template <> struct Mem<double> {
     using CT = double;
@@ -88,7 +100,7 @@ template <> struct Mem<__half> {
     static __device__ __forceinline__ void st(rsrc_t r, uint32_t v, uint32_t s, float x)
     {
         __builtin_amdgcn_raw_buffer_store_b16(
-            __builtin_bit_cast(unsigned short, __float2half_rn(x)), r, v, s, POL);
+            __builtin_bit_cast(unsigned short, __float2half_rn(as_computed(x))), r, v, s, POL);
     }
 };
 template <> struct Mem<__hip_bfloat16> {
@@ -103,7 +115,7 @@ template <> struct Mem<__hip_bfloat16> {
     static __device__ __forceinline__ void st(rsrc_t r, uint32_t v, uint32_t s, float x)
     {
         __builtin_amdgcn_raw_buffer_store_b16(
-            __builtin_bit_cast(unsigned short, __float2bfloat16(x)), r, v, s, POL);
+            __builtin_bit_cast(unsigned short, __float2bfloat16(as_computed(x))), r, v, s, POL);
     }
 };
 

@@ -172,26 +172,35 @@ inline int red_blocks(const prc_params &p)
 // ring densities per node; a wider one gives longer contiguous row segments.
 struct TileShape {
     int tx, ty;
-    int steps;  // time steps per launch: 1 (k_sweep) or 2 (k_sweep2)
+    int steps;  // time steps per launch: 1 (k_sweep), 2 (k_sweep2), 0 any (k_resident)
 };
 // Narrow shapes waste fewer threads on grids whose width is not a multiple
 // of 64 (batches of small problems); a wavefront then spans two or four rows.
 // The two-step shapes (5 and 6 also for batches) trade the collisions of two
 // extra rings per tile for half the state traffic and half the launches;
-// squarer tiles have relatively smaller rings.
-constexpr TileShape kTiles[] = {{64, 4, 1},  {64, 8, 1},  {128, 4, 1}, {32, 8, 1}, {32, 16, 1},
-                                {64, 8, 2},  {32, 16, 2}, {64, 16, 2}, {32, 32, 2}};
+// squarer tiles have relatively smaller rings.  The last entry is the
+// resident sweep: 64 x 32-node subdomains, two nodes per thread, any number
+// of steps per launch, for grids whose state fits the chip's LDS.
+constexpr TileShape kTiles[] = {{64, 4, 1},  {64, 8, 1},  {128, 4, 1}, {32, 8, 1},
+                                {32, 16, 1}, {64, 8, 2},  {32, 16, 2}, {64, 16, 2},
+                                {32, 32, 2}, {64, 32, 0}};
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 constexpr int kNumSingleStepTiles = 5;  // indices below this advance one step
 // Batches use the shapes below this index: the single-step ones and the
 // two-step shapes whose single-step twin has the same tile (64 x 8 -> 1,
 // 32 x 16 -> 4), so that one tile list serves both.
 constexpr int kNumBatchTiles = 7;
+constexpr int kResidentTile = 9;
 
-// Whether tile shape `tile` may run problem p (every shape runs every storage).
+// Whether the resident sweep can run problem p on the current device
+// (prc_resident.hip).
+bool resident_allowed(const prc_params &p);
+
+// Whether tile shape `tile` may run problem p (every sweep shape runs every
+// storage; the resident sweep needs a state that fits the LDS).
 inline bool tile_allowed(const prc_params &p, int tile)
 {
-    (void)p;
+    if (tile == kResidentTile) return resident_allowed(p);
     return tile >= 0 && tile < kNumTiles;
 }
 

@@ -62,4 +62,14 @@ inline prc_status launch_sweep_variant(const prc_params &p, const void *src, voi
 prc_status launch_sweep_wide(const prc_params &p, int tile, const void *src, void *dst,
                              hipStream_t s);
 
+// The resident sweep (prc_resident.hip): setting up its flags on the current
+// device (once, not under graph capture); nsteps time steps from src (the
+// state after an odd count in dst, after an even count back in src); and the
+// check, after the stream's work, that no launch lost a workgroup's wait
+// (clears the report).
+prc_status resident_prepare(hipStream_t s);
+prc_status launch_resident(const prc_params &p, const void *src, void *dst, int64_t nsteps,
+                           hipStream_t s);
+prc_status resident_check(hipStream_t s);
+
 }  // namespace prc

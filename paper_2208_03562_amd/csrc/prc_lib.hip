@@ -89,12 +89,16 @@ static int tile_choice(const prc_params &p)
         auto it = g_tuned.find(tune_key(p));
         if (it != g_tuned.end()) return it->second;
     }
-    // measured on MI355X: on grids that fill the chip two steps per launch
-    // pay for every storage type.  FP32: 64 x 16 tiles while the two states
-    // stay in the last-level cache, 32 x 32 for states streamed from HBM;
-    // 16-bit: 64 x 16; FP64 (twice the LDS per tile, so 512-thread tiles):
-    // 64 x 8 in the cache, 32 x 16 from HBM
+    // measured on MI355X: a grid whose state fits the LDS of the chip with
+    // one subdomain per CU runs the resident sweep (1024 x 512 FP32: 5.0
+    // against 6.2 us per step for two steps per launch); on other grids that
+    // fill the chip two steps per launch pay for every storage type.  FP32:
+    // 64 x 16 tiles while the two states stay in the last-level cache,
+    // 32 x 32 for states streamed from HBM; 16-bit: 64 x 16; FP64 (twice the
+    // LDS per tile, so 512-thread tiles): 64 x 8 in the cache, 32 x 16 from
+    // HBM
     if (p.nx >= 256 && p.ny >= 64) {
+        if (resident_allowed(p)) return kResidentTile;
         int64_t row, plane, total;
         layout(p, row, plane, total);
         const bool cached = 2 * total * (int64_t)elem_bytes(p.storage) <= kNtPairBytes;
@@ -105,7 +109,12 @@ static int tile_choice(const prc_params &p)
     return p.nx >= 256 ? 2 : 0;
 }
 
-// One launch of tile shape `tile`: kTiles[tile].steps time steps, src -> dst.
+// Steps of one resident launch when shapes are timed against each other:
+// one convergence-check interval, as the solver runs it.
+constexpr int kResidentTuneSteps = 1000;
+
+// One launch of tile shape `tile`: kTiles[tile].steps time steps, src -> dst
+// (the resident sweep: kResidentTuneSteps steps, the state back in src).
 template <typename ST, int BC>
 static prc_status launch_sweep_tile(const prc_params &p, int tile, const void *src, void *dst,
                                     hipStream_t s)
@@ -119,6 +128,7 @@ static prc_status launch_sweep_tile(const prc_params &p, int tile, const void *s
     case 6: return launch_sweep_variant<ST, BC, 32, 16, 2>(p, src, dst, s);
     case 7:
     case 8: return launch_sweep_wide(p, tile, src, dst, s);  // prc_wide.hip
+    case kResidentTile: return launch_resident(p, src, dst, kResidentTuneSteps, s);
     default: return launch_sweep_variant<ST, BC, 64, 4>(p, src, dst, s);
     }
 }
@@ -137,6 +147,8 @@ static int single_step_tile(int tile)
 static prc_status run_steps(const prc_params &p, int tile, void *f_a, void *f_b, int64_t k0,
                             int64_t n, hipStream_t s)
 {
+    if (tile == kResidentTile)  // any number of steps per launch
+        return launch_resident(p, (k0 & 1) ? f_b : f_a, (k0 & 1) ? f_a : f_b, n, s);
     prc_status st = PRC_OK;
     int64_t k = k0;
     const int64_t end = k0 + n;
@@ -339,6 +351,7 @@ prc_status prc_step(const prc_params *p, void *f_a, void *f_b, int64_t nsteps, h
     if (nsteps < 0) return fail(PRC_EINVAL, "nsteps < 0");
     int64_t k = 0;
     const int tile = tile_choice(*p);
+    if (tile == kResidentTile && (st = resident_prepare(stream)) != PRC_OK) return st;
     // Long runs replay a captured graph of graph_steps() steps (a multiple of
     // four, so the newest state is back in f_a after every replay whether the
     // shape takes one or two steps per launch).  Not while the caller's stream
@@ -346,7 +359,9 @@ prc_status prc_step(const prc_params *p, void *f_a, void *f_b, int64_t nsteps, h
     const int gsteps = graph_steps();
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     HIP_TRY(hipStreamIsCapturing(stream, &cap));
-    if (gsteps > 0 && cap == hipStreamCaptureStatusNone && nsteps >= 2 * gsteps) {
+    // (the resident sweep takes any number of steps in one launch: no graph)
+    if (tile != kResidentTile && gsteps > 0 && cap == hipStreamCaptureStatusNone &&
+        nsteps >= 2 * gsteps) {
         hipGraphExec_t exec = nullptr;
         if ((st = get_graph(*p, tile, f_a, f_b, gsteps, &exec)) != PRC_OK) return st;
         for (; k + gsteps <= nsteps; k += gsteps) HIP_TRY(hipGraphLaunch(exec, stream));
@@ -367,6 +382,7 @@ prc_status prc_residual(const prc_params *p, const void *f, double *u_prev, void
     HIP_TRY(hipMemcpyAsync(out, sc + 4 * kRedMaxBlocks, 4 * sizeof(double),
                            hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
+    if ((st = resident_check(stream)) != PRC_OK) return st;
     out[2] += p->rho0 * (double)p->nx * (double)p->ny;  // rest part of the mass
     return PRC_OK;
 }
@@ -444,6 +460,7 @@ prc_status prc_tune(const prc_params *p, int32_t *tile_out, hipStream_t stream)
     if (he == hipSuccess) he = hipEventCreate(&e1);
     for (int t = 0; t < kNumTiles && he == hipSuccess && st == PRC_OK; ++t) {
         if (!tile_allowed(*p, t)) continue;
+        if (t == kResidentTile && resident_prepare(stream) != PRC_OK) continue;
         for (int k = 0; k < kWarm + kTimed && st == PRC_OK; ++k) {
             if (k == kWarm) he = hipEventRecord(e0, stream);
             st = PRC_DISPATCH(*p, launch_sweep_tile, *p, t, (k & 1) ? b : a, (k & 1) ? a : b,
@@ -454,7 +471,9 @@ prc_status prc_tune(const prc_params *p, int32_t *tile_out, hipStream_t stream)
         if (he == hipSuccess) he = hipEventSynchronize(e1);
         float ms = 0.0f;
         if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
-        ms /= (float)kTiles[t].steps;  // per time step
+        // a resident launch that lost a wait does not count
+        if (he == hipSuccess && t == kResidentTile && resident_check(stream) != PRC_OK) continue;
+        ms /= (float)(t == kResidentTile ? kResidentTuneSteps : kTiles[t].steps);  // per step
         if (he == hipSuccess && (best < 0 || ms < best_ms)) {
             best = t;
             best_ms = ms;

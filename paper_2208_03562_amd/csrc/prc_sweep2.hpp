@@ -41,11 +41,14 @@ template <> struct LdsVal<float> {
     static __device__ __forceinline__ float get(float x) { return x; }
 };
 template <> struct LdsVal<__half> {
-    static __device__ __forceinline__ __half put(float x) { return __float2half_rn(x); }
+    static __device__ __forceinline__ __half put(float x) { return __float2half_rn(as_computed(x)); }
     static __device__ __forceinline__ float get(__half x) { return __half2float(x); }
 };
 template <> struct LdsVal<__hip_bfloat16> {
-    static __device__ __forceinline__ __hip_bfloat16 put(float x) { return __float2bfloat16(x); }
+    static __device__ __forceinline__ __hip_bfloat16 put(float x)
+    {
+        return __float2bfloat16(as_computed(x));
+    }
     static __device__ __forceinline__ float get(__hip_bfloat16 x) { return __bfloat162float(x); }
 };
 

@@ -241,11 +241,19 @@ def test_step_rejects_bad_buffers_before_launching(a, b, n):
 
 
 def test_tile_info():
-    shapes = [capi.prc_tile_info(t) for t in range(9)]
+    shapes = [capi.prc_tile_info(t) for t in range(10)]
     assert shapes[0] == (64, 4, 1) and shapes[8] == (32, 32, 2)
-    assert [s[2] for s in shapes] == [1] * 5 + [2] * 4
+    assert [s[2] for s in shapes] == [1] * 5 + [2] * 4 + [0]  # 0: resident, any count
+    assert shapes[9][:2] == (64, 32)
     with pytest.raises(capi.PrcError):
-        capi.prc_tile_info(9)
+        capi.prc_tile_info(10)
+
+
+def test_resident_tile_needs_a_device():
+    """Whether the resident sweep fits is a property of the device (its
+    compute units and LDS): without one it is refused."""
+    with pytest.raises(capi.PrcError):
+        capi.prc_set_tile(base(), 9)
 
 
 def test_batch_tile_range():

@@ -1,0 +1,83 @@
+"""The resident sweep (tile 9): many steps per launch with the state held in
+LDS, subdomains exchanging their edges through memory.  Every node passes
+through the single-step arithmetic with the state rounded to the storage type
+between steps, so the results must be the single-step sweep's bits -- for
+every boundary type, 32- and 16-bit storage, both sweep variants and frames,
+grids smaller than a subdomain and with ragged edges, odd and even step
+counts, captured graph replays, and the 1024 x 512 cavity that takes one
+subdomain per compute unit."""
+import pytest
+import torch
+
+import workloads
+from tests.common import lib_params, spec
+
+pytestmark = pytest.mark.gpu
+
+RESIDENT = 9
+
+CASES = [
+    ("cavity", 2.0, 0.5, dict(u_lid=0.05), [(150, 37), (7, 5), (3, 70), (130, 260)]),
+    ("cavity", 0.5, 0.1, dict(u_lid=0.02, fx=1e-6), [(150, 37), (64, 32)]),
+    ("periodic", 1.0, 0.3, dict(fx=1e-5, fy=-2e-5), [(128, 64), (64, 96)]),
+    ("channel", 4.0, 1.0, dict(u_lid=0.03, frame=1), [(128, 37), (64, 70)]),
+    ("cavity", 1.0, 0.7, dict(u_lid=0.04, corrections=3, omega_3=1.2), [(200, 90)]),
+]
+
+
+def run(s, tile, nsteps, seed):
+    from paper_2208_03562_amd import capi, solver
+    sol = solver.Solver(lib_params(s))
+    capi.prc_set_tile(sol.p, tile)
+    sol.set_state(workloads.deviation_noise(s["nx"], s["ny"], seed, 1e-3))
+    sol.step(nsteps)
+    out = sol.get_state()
+    sol.residual()  # reports a resident launch that lost a wait
+    capi.prc_set_tile(sol.p, -1)
+    capi.prc_release_graphs()
+    return out
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}-r{c[1]}-g{c[2]}")
+def test_resident_sweep_gives_the_single_step_bits(storage, case):
+    bc, r, gamma, extra, grids = case
+    for nx, ny in grids:
+        s = spec(nx, ny, r, gamma, omega_nu=1.3, bc=bc, storage=storage, **extra)
+        for nsteps in (1, 2, 7):
+            ref = run(s, 0, nsteps, seed=nx + ny)
+            got = run(s, RESIDENT, nsteps, seed=nx + ny)
+            assert bool((got == ref).all()), (nx, ny, nsteps)
+
+
+def test_resident_graph_replays():
+    """136 steps: two replays of a 64-step graph (one resident launch each)
+    and 8 more steps."""
+    s = spec(300, 140, 2.0, 0.2, re=500.0, omega_nu=None, u_lid=0.05, storage="f32")
+    ref = run(s, 1, 136, seed=9)
+    assert bool((run(s, RESIDENT, 136, seed=9) == ref).all())
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_resident_1024x512_cavity(storage):
+    """One 64 x 32 subdomain per compute unit; 300 steps against the
+    single-step sweep, bit for bit, and a residual that reports no lost
+    wait."""
+    w = workloads.CAVITY_1024x512_F32_MA006
+    s = spec(w.nx, w.ny, w.r, w.gamma, re=w.re, omega_nu=None, u_lid=w.u_lid, storage=storage)
+    ref = run(s, 1, 300, seed=3)
+    got = run(s, RESIDENT, 300, seed=3)
+    assert bool(torch.isfinite(got.float()).all())
+    assert bool((got == ref).all())
+
+
+def test_resident_rejects_grids_beyond_the_lds():
+    """A state too large for one subdomain per compute unit, FP64, and a
+    periodic side that cuts a subdomain are refused."""
+    from paper_2208_03562_amd import capi, solver
+    for s in (spec(4096, 2048, 1.0, 1.0, u_lid=0.05, storage="f32"),
+              spec(128, 64, 1.0, 1.0, u_lid=0.05, storage="f64"),
+              spec(100, 64, 1.0, 1.0, bc="channel", u_lid=0.05, storage="f32")):
+        p = lib_params(s)
+        with pytest.raises(capi.PrcError):
+            capi.prc_set_tile(p, RESIDENT)
