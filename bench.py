@@ -24,6 +24,7 @@ import workloads  # noqa: E402
 BYTES_PER_NODE = {"f64": 144, "f32": 72, "f16": 36, "bf16": 36}
 STORAGE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 HBM_PEAK_GBS = 8000.0
+VALU_PEAK_GINST_S = 614.4  # wave64 VALU instructions per second, 256 CUs x 4 SIMDs x 2.4 GHz / 4
 CHECK_EVERY = 1000
 
 
@@ -253,7 +254,8 @@ def run_cpu_baseline(w: workloads.Cavity, budget_s: float):
 def pmc_run(steps: int):
     """Short fixed workload for hardware-counter runs: a plain device copy of
     256 MiB each way (the reference for scaling byte counters), then `steps`
-    sweeps of the 1024x512 and of the 4096x2048 FP32 cavity."""
+    steps of the 1024x512 FP32 cavity (one launch of the resident sweep when
+    the tuner picks it) and min(steps, 64) of the 4096x2048 one."""
     import torch
     from paper_2208_03562_amd import solver
 
@@ -270,9 +272,10 @@ def pmc_run(steps: int):
         from paper_2208_03562_amd import capi
         capi.prc_tune(p)  # same tile shape as the timed benchmark
         sol = solver.Solver(p, device="cuda:0")
-        sol.step(steps)
+        n = steps if w is PMC_GRIDS[0] else min(steps, 64)
+        sol.step(n)
         torch.cuda.synchronize()
-        log(f"[pmc] {steps} sweeps of {w.name} done")
+        log(f"[pmc] {n} steps of {w.name} done")
         del sol
 
 
@@ -320,6 +323,25 @@ def traffic_from_counters(pmc_dir: str):
     rec = {"source_hash": build.source_hash(), "copy_scale": {}, "bytes_per_launch": {},
            "note": "HBM bytes per launch of each sweep instance: FETCH_SIZE and WRITE_SIZE "
                    "(KiB per dispatch) each scaled by its reading for a 256 MiB device copy"}
+    def per_kernel(rows, ctr):
+        """{grid name: {kernel: mean counter value per dispatch}} of the sweeps"""
+        out = {}
+        for w in PMC_GRIDS:
+            groups = collections.defaultdict(list)
+            # sweeps launch a thread per node; the resident sweep 1024 threads
+            # per 64 x 32 subdomain, in whole groups of eight
+            subs = -(-w.nx // 64) * -(-w.ny // 32)
+            resident_threads = -(-subs // 8) * 8 * 1024
+            for r in rows:
+                name, grid = r["Kernel_Name"], int(r["Grid_Size"])
+                if r["Counter_Name"] == ctr and (
+                        ("k_sweep" in name and grid == w.nx * w.ny)
+                        or ("k_resident" in name and grid == resident_threads)):
+                    groups[name.split("(")[0].replace("void ", "")].append(
+                        float(r["Counter_Value"]))
+            out[w.name] = {k: sum(v) / len(v) for k, v in groups.items()}
+        return out
+
     per = collections.defaultdict(lambda: collections.defaultdict(float))
     for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
         rows = list(csv.DictReader(open(os.path.join(pmc_dir, ctr, "run_counter_collection.csv"))))
@@ -329,17 +351,20 @@ def traffic_from_counters(pmc_dir: str):
         copy = [v for g, v in copy if g == big]
         scale = PMC_COPY_BYTES / (sum(copy) / len(copy) * 1024.0)
         rec["copy_scale"][ctr] = round(scale, 5)
-        for w in PMC_GRIDS:
-            groups = collections.defaultdict(list)
-            for r in rows:
-                if ("k_sweep" in r["Kernel_Name"] and r["Counter_Name"] == ctr
-                        and int(r["Grid_Size"]) == w.nx * w.ny):
-                    groups[r["Kernel_Name"].split("(")[0].replace("void ", "")].append(
-                        float(r["Counter_Value"]))
-            for name, vals in groups.items():
-                per[w.name][name] += sum(vals) / len(vals) * 1024.0 * scale
+        for wname, kernels in per_kernel(rows, ctr).items():
+            for name, v in kernels.items():
+                per[wname][name] += v * 1024.0 * scale
     for wname, kernels in per.items():
         rec["bytes_per_launch"][wname] = {k: int(round(v)) for k, v in sorted(kernels.items())}
+    # instructions issued per launch (wave instructions, all CUs), if a third
+    # run counted them
+    sq = os.path.join(pmc_dir, "SQ", "run_counter_collection.csv")
+    if os.path.exists(sq):
+        rows = list(csv.DictReader(open(sq)))
+        for ctr, key in (("SQ_INSTS_VALU", "valu_insts_per_launch"),
+                         ("SQ_INSTS_LDS", "lds_insts_per_launch")):
+            rec[key] = {wname: {k: int(round(v)) for k, v in sorted(kernels.items())}
+                        for wname, kernels in per_kernel(rows, ctr).items()}
     path = os.path.join(ROOT, "profiles", "traffic.json")
     with open(path, "w") as fh:
         json.dump(rec, fh, indent=1)
@@ -394,10 +419,10 @@ def trace_summary(trace_dir: str):
               f"{v[len(v) // 2] / 1e3:.3f} | {v[0] / 1e3:.3f} |")
 
 
-def measured_traffic(w: workloads.Cavity, kernel: str):
-    """HBM bytes per launch of sweep instance `kernel` on grid w from the
-    committed counter summary, if it was taken on the current library code
-    (else None)."""
+def measured_traffic(w: workloads.Cavity, kernel: str, key: str = "bytes_per_launch"):
+    """HBM bytes per launch of sweep instance `kernel` on grid w (or another
+    per-launch count, `key`) from the committed counter summary, if it was
+    taken on the current library code (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         rec = json.load(open(path))
@@ -406,7 +431,7 @@ def measured_traffic(w: workloads.Cavity, kernel: str):
     from paper_2208_03562_amd import build
     if rec.get("source_hash") != build.source_hash():
         return None
-    return rec.get("bytes_per_launch", {}).get(w.name, {}).get(kernel)
+    return rec.get(key, {}).get(w.name, {}).get(kernel)
 
 
 def main():
@@ -477,7 +502,21 @@ def main():
         w.nx, w.ny, w.r, w.gamma, re=w.re, u_lid=w.u_lid, storage=STORAGE[w.storage]))
     kernel = sweep_kernel_name(w.storage, 0, main_res["tile"], state_bytes)
     traffic = measured_traffic(w, kernel)
+    valu_insts = measured_traffic(w, kernel, "valu_insts_per_launch")
     nodes = w.nx * w.ny
+    kernel_us = main_res["sweep_us"] * per_launch
+    valu = None
+    if valu_insts:
+        # VALU issue: a wave64 instruction takes 4 cycles of a 16-lane SIMD;
+        # 256 CUs x 4 SIMDs at 2.4 GHz issue 614.4 G of them per second
+        # (FP32 without packed instructions)
+        achieved = valu_insts / (kernel_us * 1e-6) / 1e9
+        valu = {"insts_per_launch": valu_insts,
+                "insts_per_node_update": round(valu_insts * 64 / (nodes * per_launch), 1),
+                "achieved_ginst_s": round(achieved, 1), "peak_ginst_s": VALU_PEAK_GINST_S,
+                "frac": round(achieved / VALU_PEAK_GINST_S, 4),
+                "note": "wave instructions (SQ_INSTS_VALU, committed counter run) / this run's "
+                        "launch time; peak: 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles"}
 
     out = {
         "metric": "MLUPS",
@@ -502,7 +541,8 @@ def main():
                      "algorithmic_bytes": BYTES_PER_NODE[w.storage] * nodes * per_launch,
                      "kernel": kernel,
                      "steps_per_launch": per_launch,
-                     "kernel_us": round(main_res["sweep_us"] * per_launch, 3),
+                     "kernel_us": round(kernel_us, 3),
+                     "valu": valu,
                      "note": f"72 B per node update (9 FP32 reads + 9 FP32 writes) x {nodes} "
                              f"nodes x {per_launch} step(s) per launch; achieved = those bytes / "
                              "launch time.  The resident sweep keeps the state in LDS for all "
