@@ -134,9 +134,11 @@ __device__ __forceinline__ void reflect(const Coef<CT> &c, ST (*P)[SY + 4][SX + 
 }
 
 // One subdomain per workgroup, two nodes per thread.  Each thread owns one
-// node at least two nodes from the subdomain's boundary and a second node,
-// another such one (threads below B0) or an edge node (the rest), so that
-// per step:
+// node at least two nodes from the subdomain's boundary (an inner node) and
+// a second node that collides early for threads below L0 (another inner
+// node) and late for the others (the edge nodes, and inner nodes for the
+// rest of them).  The late half is waves 8-15, two on each SIMD, so every
+// SIMD collides six waves' nodes early and two late.  Per step:
 //   X  streaming and densities of the nodes whose sources are the
 //      subdomain's own (every node but the outermost ring)
 //   Y  the neighbours' edges of the previous step are loaded (in flight)
@@ -144,7 +146,7 @@ __device__ __forceinline__ void reflect(const Coef<CT> &c, ST (*P)[SY + 4][SX + 
 //      of LDS
 //   Z  streaming and densities of the outermost ring and of the ring around
 //      the subdomain
-//   W  the edge nodes collide; the new state goes into LDS, the edges into
+//   W  the late nodes collide; the new state goes into LDS, the edges into
 //      the exchange blocks.
 template <typename ST, int BC, bool FORCE, bool ALL>
 __global__ void __launch_bounds__(kResidentThreads)
@@ -157,10 +159,11 @@ __global__ void __launch_bounds__(kResidentThreads)
     constexpr int HALO = 4 * W2 + 4 * SY;
     constexpr int FILL = (N2 + T - 1) / T;
     constexpr int IW = SX - 4, NI = (SX - 4) * (SY - 4);  // nodes two or more from the boundary
-    constexpr int B0 = NI - T;                             // first thread with an edge node
+    constexpr int L0 = T / 2;                              // first thread whose second node is late
+    constexpr int NE = 4 * SX + 4 * (SY - 4);              // edge nodes
+    constexpr int LI = T - L0 - NE;                        // late inner nodes
     constexpr uint32_t E = sizeof(ST);
-    static_assert(NI >= T && NI + (4 * SX + 4 * (SY - 4)) == 2 * T && HALO <= T,
-                  "subdomain shape");
+    static_assert(NI + NE == 2 * T && LI >= 0 && HALO <= T, "subdomain shape");
     __shared__ ST P[9][H2][W2];        // post-collision state, origin (2, 2)
     __shared__ CT D[SY + 2][SX + 2];   // densities, origin (1, 1)
     __shared__ uint64_t s_base;
@@ -223,11 +226,11 @@ __global__ void __launch_bounds__(kResidentThreads)
     bool act[2], own[2];
     si[0] = 2 + t % IW;
     sj[0] = 2 + t / IW;
-    if (t < B0) {
+    if (t < L0 + LI) {  // inner nodes T .. NI - 1
         si[1] = 2 + (t + T) % IW;
         sj[1] = 2 + (t + T) / IW;
     } else {
-        edge_pos<SX, SY>(t - B0, si[1], sj[1]);
+        edge_pos<SX, SY>(t - L0 - LI, si[1], sj[1]);
     }
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
@@ -323,7 +326,7 @@ __global__ void __launch_bounds__(kResidentThreads)
                 h[a] = __builtin_amdgcn_raw_buffer_load_b64(rx, qaddr + a * qstride, 0, kAgent);
         }
         if (act[0]) collide_at(si[0], sj[0], d[0]);
-        if (t < B0 && act[1]) collide_at(si[1], sj[1], d[1]);
+        if (t < L0 && act[1]) collide_at(si[1], sj[1], d[1]);
         if (load) {
             uint32_t miss = 0;
 #pragma unroll
@@ -379,7 +382,7 @@ __global__ void __launch_bounds__(kResidentThreads)
         // W: the edge nodes collide; the new state into LDS (and its ghost
         // slots), the edges into the exchange blocks tagged with this step
         // (every node into the output state at the last step)
-        if (t >= B0 && act[1]) collide_at(si[1], sj[1], d[1]);
+        if (t >= L0 && act[1]) collide_at(si[1], sj[1], d[1]);
         const uint32_t xb = (uint32_t)(((s & 1) * ntiles + sub) * kXchElems) * kXchPair;
         const uint32_t tag = (uint32_t)(base + (uint64_t)s);
 #pragma unroll
@@ -397,7 +400,7 @@ __global__ void __launch_bounds__(kResidentThreads)
                 const uint32_t o = (uint32_t)(y0 + j) * c.row_bytes + (uint32_t)(x0 + i) * E;
 #pragma unroll
                 for (int a = 0; a < 9; ++a) Mem<ST>::st(ro, o, a * c.plane_bytes, d[m][a]);
-            } else if (m == 1 && t >= B0) {
+            } else if (m == 1 && t >= L0 + LI) {
                 if (j < 2 || j >= SY - 2) {  // a row block
                     const uint32_t o =
                         xb + (uint32_t)((j < 2 ? kXchBot + j * SX : kXchTop + (j - SY + 2) * SX) + i) *
