@@ -4,8 +4,8 @@ through the single-step arithmetic with the state rounded to the storage type
 between steps, so the results must be the single-step sweep's bits -- for
 every boundary type, 32- and 16-bit storage, both sweep variants and frames,
 grids smaller than a subdomain and with ragged edges, odd and even step
-counts, captured graph replays, and the 1024 x 512 cavity that takes one
-subdomain per compute unit."""
+counts, long calls, replays of a graph the caller captured, and the
+1024 x 512 cavity that takes one subdomain per compute unit."""
 import pytest
 import torch
 
@@ -50,9 +50,9 @@ def test_resident_sweep_gives_the_single_step_bits(storage, case):
             assert bool((got == ref).all()), (nx, ny, nsteps)
 
 
-def test_resident_graph_replays():
-    """136 steps: two replays of a 64-step graph (one resident launch each)
-    and 8 more steps."""
+def test_resident_long_call():
+    """136 steps in one call: one resident launch (the resident sweep takes
+    any number of steps per launch; no launch graph is cached for it)."""
     s = spec(300, 140, 2.0, 0.2, re=500.0, omega_nu=None, u_lid=0.05, storage="f32")
     ref = run(s, 1, 136, seed=9)
     assert bool((run(s, RESIDENT, 136, seed=9) == ref).all())
@@ -81,3 +81,46 @@ def test_resident_rejects_grids_beyond_the_lds():
         p = lib_params(s)
         with pytest.raises(capi.PrcError):
             capi.prc_set_tile(p, RESIDENT)
+
+
+def test_resident_steps_captured_by_the_caller():
+    """A caller captures prc_step (one resident launch of 64 steps) into a
+    graph of its own and replays it three times, with eager work and host
+    synchronisation between the replays: the base of the step tags lives on
+    the device, so every replay continues the count, and after each replay
+    the state equals that of 64 more single steps, bit for bit."""
+    from paper_2208_03562_amd import capi, solver
+    nx, ny = 200, 90
+    s = spec(nx, ny, 2.0, 0.5, omega_nu=1.3, u_lid=0.05, storage="f32")
+    p = lib_params(s)
+    noise = workloads.deviation_noise(nx, ny, 5, 1e-3)
+    try:
+        capi.prc_set_tile(p, 1)  # reference: single steps
+        ref = solver.Solver(p)
+        ref.set_state(noise)
+        ref.step(2)
+        want = []
+        for _ in range(3):
+            ref.step(64)
+            want.append(ref.get_state())
+        del ref
+
+        capi.prc_set_tile(p, RESIDENT)
+        stream = torch.cuda.Stream()
+        sol = solver.Solver(p, stream=stream)
+        sol.set_state(noise)
+        sol.step(2)  # the first resident call sets up its counters, outside capture
+        stream.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            sol.step(64)  # 64 steps: the newest state is back in the same buffer
+        for k in range(3):
+            g.replay()
+            sol.residual()  # synchronises; reports a lost wait
+            scratch = torch.ones(1 << 20, device="cuda:0").sum()  # eager work between replays
+            torch.cuda.synchronize()
+            assert float(scratch) == float(1 << 20)
+            assert bool((sol.get_state() == want[k]).all()), k
+    finally:
+        capi.prc_set_tile(p, -1)
+        capi.prc_release_graphs()
