@@ -194,7 +194,9 @@ prc_status prc_solve(const prc_params *p, void *f_a, void *f_b, double *u_prev,
  * most one subdomain per compute unit, a periodic side a multiple of the
  * subdomain; see prc_tile_info) for this problem's storage,
  * boundaries and grid size, on two scratch state buffers that the call
- * allocates and frees itself (hipMalloc/hipFree), and use the fastest (per time step) for
+ * allocates and frees itself (hipMalloc/hipFree; timing the resident sweep
+ * also sets up its per-device counters and exchange buffer, which stay), and
+ * use the fastest (per time step) for
  * every later sweep of a problem with the same storage, boundaries and grid
  * size in this process.  The tile shape changes only the speed, not the
  * results.  tile_out (host, may be NULL) receives the chosen index.  Without
