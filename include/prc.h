@@ -143,7 +143,10 @@ prc_status prc_init(const prc_params *p, void *f, hipStream_t stream);
  * even and f_b when k is odd, so after nsteps steps the newest state is in
  * f_a when nsteps is even and in f_b when it is odd (the other buffer holds
  * an earlier state; the resident sweep, which keeps the state in LDS between
- * steps, may leave it as it was).  One step = streaming
+ * steps, may leave it as it was).  Resident-sweep calls on one device must
+ * not overlap in time (e.g. on two streams at once): they share the device's
+ * exchange buffer and need every compute unit; if they do, prc_residual
+ * reports the failed wait and the states are invalid.  One step = streaming
  * with boundaries (Appendix A, "stream"; moving-wall bounce-back as noted at
  * the end of Appendix A), the hydrodynamic fields of the streamed state
  * (eq. hydrodynamicfields), the density gradient, and the collision.  f_a and
