@@ -20,8 +20,10 @@
  *    prc_step (until prc_release_graphs or process exit), the scratch
  *    states prc_tune allocates and frees within the call, and, on a device
  *    where the resident sweep (tile 9) runs, its counters and exchange
- *    buffer (about 28 MB, allocated and cleared once, kept until process
- *    exit).  A batch owns its
+ *    buffer (about 28 MB, allocated and cleared once), an 8-byte pinned host
+ *    word and an event, kept until prc_release_resident or process exit.
+ *    Process-wide state besides: the tile choices of prc_tune/prc_set_tile
+ *    and the mode of prc_set_streamed.  A batch owns its
  *    small tables and graphs until prc_batch_destroy; prc_serve allocates its
  *    request pool for the duration of the call.
  *  - Calls are ordered on the HIP stream passed in (0 = null stream) and are
@@ -143,10 +145,15 @@ prc_status prc_init(const prc_params *p, void *f, hipStream_t stream);
  * even and f_b when k is odd, so after nsteps steps the newest state is in
  * f_a when nsteps is even and in f_b when it is odd (the other buffer holds
  * an earlier state; the resident sweep, which keeps the state in LDS between
- * steps, may leave it as it was).  Resident-sweep calls on one device must
- * not overlap in time (e.g. on two streams at once): they share the device's
- * exchange buffer and need every compute unit; if they do, prc_residual
- * reports the failed wait and the states are invalid.  One step = streaming
+ * steps, may leave it as it was).  Resident-sweep launches on one device
+ * share its exchange buffer and need every compute unit: a launch on another
+ * stream than the device's latest resident launch first waits for that one
+ * (an event), so calls on several streams run one after the other.  Launches
+ * captured into a graph are not ordered this way: replays of such graphs on
+ * one device must not overlap.  A launch that nevertheless loses a
+ * workgroup's wait (its state is then invalid) is reported by the next
+ * prc_step, prc_macros, prc_residual, prc_solve or prc_resident_status on
+ * the device (PRC_EHIP), before anything else runs.  One step = streaming
  * with boundaries (Appendix A, "stream"; moving-wall bounce-back as noted at
  * the end of Appendix A), the hydrodynamic fields of the streamed state
  * (eq. hydrodynamicfields), the density gradient, and the collision.  f_a and
@@ -163,7 +170,7 @@ prc_status prc_step(const prc_params *p, void *f_a, void *f_b, int64_t nsteps,
  * u_y plane); scratch: device, prc_scratch_bytes; out: host double[4].
  * Synchronises the stream.  The sums are reproduced bit for bit run to run.
  * Returns PRC_EHIP (and clears the report) if a resident sweep on this device
- * gave up waiting for a neighbouring subdomain since the last check (every
+ * gave up waiting for a neighbouring subdomain since the last report (every
  * subdomain must have a compute unit at once; the state is then invalid). */
 prc_status prc_residual(const prc_params *p, const void *f, double *u_prev,
                         void *scratch, double out[4], hipStream_t stream);
@@ -230,8 +237,42 @@ prc_status prc_tile_info(int32_t tile, int32_t *tx, int32_t *ty, int32_t *steps)
  * were captured with until prc_release_graphs. */
 prc_status prc_set_tile(const prc_params *p, int32_t tile);
 
-/* Drop the launch graphs cached by prc_step (they hold no user memory). */
+/* Drop the launch graphs cached by prc_step (they hold no user memory).
+ * Waits for the devices they were captured on to finish their work first
+ * (a replay may still be running).  A graph that another thread is
+ * replaying at that moment is destroyed once that call has enqueued it. */
 prc_status prc_release_graphs(void);
+
+/* Free the current device's resident-sweep counters, exchange buffer,
+ * pinned report word and ordering event (see the conventions above), after
+ * synchronising the device.  The next resident launch on the device sets
+ * them up again.  PRC_OK when nothing was set up. */
+prc_status prc_release_resident(void);
+
+/* Whether a resident-sweep launch on the current device lost a workgroup's
+ * wait (a subdomain that got no compute unit while its neighbours waited for
+ * it; its state is invalid) since the last report: PRC_EHIP, once per
+ * report, else PRC_OK.  Reads a pinned host word that the failing launch
+ * writes: it does not synchronise, so a launch still running is reported
+ * only by a later call (prc_step, prc_macros, prc_residual and prc_solve
+ * make the same check themselves before launching or after synchronising). */
+prc_status prc_resident_status(void);
+
+/* How long a workgroup of a later resident launch (in this process) waits
+ * for a neighbour's value before it gives up and the launch is reported as
+ * failed: ticks of the GPU's 100 MHz real-time clock, -1 for the default
+ * (2^26 ticks, about 0.67 s; a neighbour that has a compute unit delivers
+ * within microseconds).  A small value makes launches fail on purpose, for
+ * tests of the report.  PRC_EINVAL below -1.  Host only. */
+prc_status prc_set_resident_wait(int64_t ticks);
+
+/* Cache policy for the two state buffers of every later sweep in the
+ * process: -1 (default) by size (non-temporal stores, and the load order of
+ * the 1024-thread two-step tiles meant for states streamed from HBM, when
+ * the two states exceed 160 MB), 0 never, 1 always.  Changes speed only,
+ * never a result; cached launch graphs keep the mode they were captured
+ * with.  PRC_EINVAL for another value.  Host only. */
+prc_status prc_set_streamed(int32_t mode);
 
 /* ---- Batches: many independent problems advanced together -------------
  *

@@ -102,6 +102,10 @@ _PROTOS = {
                                      ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(ctypes.c_int32)]),
     "prc_release_graphs": (ctypes.c_int, []),
+    "prc_release_resident": (ctypes.c_int, []),
+    "prc_resident_status": (ctypes.c_int, []),
+    "prc_set_streamed": (ctypes.c_int, [ctypes.c_int32]),
+    "prc_set_resident_wait": (ctypes.c_int, [ctypes.c_int64]),
     "prc_last_error": (ctypes.c_char_p, []),
     "prc_batch_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_VP)]),
     "prc_batch_destroy": (ctypes.c_int, [_VP]),
@@ -227,6 +231,23 @@ def prc_solve(p: prc_params, f_a: int, f_b: int, u_prev: int, scratch: int, tol:
 
 def prc_release_graphs() -> None:
     _check("prc_release_graphs", lib().prc_release_graphs())
+
+
+def prc_release_resident() -> None:
+    _check("prc_release_resident", lib().prc_release_resident())
+
+
+def prc_resident_status() -> None:
+    """Raises PrcError (PRC_EHIP) once for a resident launch that lost a wait."""
+    _check("prc_resident_status", lib().prc_resident_status())
+
+
+def prc_set_streamed(mode: int) -> None:
+    _check("prc_set_streamed", lib().prc_set_streamed(int(mode)))
+
+
+def prc_set_resident_wait(ticks: int) -> None:
+    _check("prc_set_resident_wait", lib().prc_set_resident_wait(int(ticks)))
 
 
 def prc_last_error() -> str:

@@ -11,6 +11,7 @@
 #pragma once
 
 #include <cmath>
+#include <atomic>
 #include <cstdint>
 
 #include "prc.h"
@@ -22,6 +23,10 @@ constexpr int kXcds = 8;
 // Two state buffers larger than this do not stay in the 256 MB last-level
 // cache from one sweep to the next: their stores are non-temporal.
 constexpr int64_t kNtPairBytes = (int64_t)160 << 20;
+// Process-wide override of that choice (prc_set_streamed): -1 by size, 0
+// never, 1 always.  It changes cache policies and the load order of the
+// 1024-thread two-step tiles, never a result.
+inline std::atomic<int> g_streamed_mode{-1};
 
 template <typename CT>
 struct Coef {
@@ -85,7 +90,8 @@ inline Coef<CT> make_coef(const prc_params &p, int64_t row_stride, int64_t plane
     c.state_bytes = (uint32_t)(total * elem);
     c.corr = p.corrections;
     c.frame = p.frame;
-    c.nt = 2 * total * elem > kNtPairBytes;
+    const int mode = g_streamed_mode.load(std::memory_order_relaxed);
+    c.nt = mode >= 0 ? mode : 2 * total * elem > kNtPairBytes;
     c.r = CT(r);
     c.r2 = CT(r * r);
     c.hinv_r = CT(0.5 / r);

@@ -64,12 +64,18 @@ prc_status launch_sweep_wide(const prc_params &p, int tile, const void *src, voi
 
 // The resident sweep (prc_resident.hip): setting up its flags on the current
 // device (once, not under graph capture); nsteps time steps from src (the
-// state after an odd count in dst, after an even count back in src); and the
-// check, after the stream's work, that no launch lost a workgroup's wait
-// (clears the report).
+// state after an odd count in dst, after an even count back in src), after
+// the latest resident launch on the device if that was on another stream;
+// the report, without synchronising, of a launch that lost a workgroup's wait
+// (PRC_EHIP once per such report; launches still running may report later);
+// and the release of the device's resident buffers (after a device
+// synchronise).
 prc_status resident_prepare(hipStream_t s);
 prc_status launch_resident(const prc_params &p, const void *src, void *dst, int64_t nsteps,
                            hipStream_t s);
-prc_status resident_check(hipStream_t s);
+prc_status resident_report();
+prc_status resident_release();
+// wait limit of later resident launches, in 100 MHz ticks (-1: the default)
+prc_status resident_set_wait(int64_t ticks);
 
 }  // namespace prc

@@ -20,6 +20,7 @@
 #include <cstdlib>
 #include <algorithm>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <unordered_map>
@@ -200,45 +201,66 @@ static prc_status launch_residual(const prc_params &p, const void *f, double *u_
 
 // --------------------------------------------------------- launch graphs --
 // prc_step replays captured graphs of sweeps for long runs: one graph per
-// (device, problem, buffer pair), cached until prc_release_graphs().
+// (device, problem, buffer pair), cached until prc_release_graphs(); when the
+// cache is full the least recently used graph leaves it.  A caller holds its
+// entry while replaying it, and an entry is destroyed only after its device
+// has finished every replay.
 constexpr size_t kGraphCacheMax = 32;
 
 static_assert(sizeof(prc_params) == 8 + 11 * 8 + 4 * 4, "prc_params has no padding");
 
 struct GraphEntry {
-    hipGraph_t graph;
-    hipGraphExec_t exec;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int dev = 0;
+    uint64_t used = 0;  // cache clock of the latest lookup
+    GraphEntry() = default;
+    GraphEntry(const GraphEntry &) = delete;
+    GraphEntry &operator=(const GraphEntry &) = delete;
+    ~GraphEntry()
+    {
+        // replays still in flight must finish before the exec goes away
+        int cur = -1;
+        const bool switch_dev = hipGetDevice(&cur) == hipSuccess && cur != dev;
+        if (switch_dev) (void)hipSetDevice(dev);
+        (void)hipDeviceSynchronize();
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (switch_dev) (void)hipSetDevice(cur);
+    }
 };
 static std::mutex g_graph_mu;
-static std::unordered_map<std::string, GraphEntry> g_graphs;
-
-static void destroy_graphs_locked()
-{
-    for (auto &kv : g_graphs) {
-        (void)hipGraphExecDestroy(kv.second.exec);
-        (void)hipGraphDestroy(kv.second.graph);
-    }
-    g_graphs.clear();
-}
+static std::unordered_map<std::string, std::shared_ptr<GraphEntry>> g_graphs;
+static uint64_t g_graph_clock = 0;
 
 static prc_status get_graph(const prc_params &p, int tile, void *f_a, void *f_b, int nsteps,
-                            hipGraphExec_t *out)
+                            std::shared_ptr<GraphEntry> *out)
 {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
+    const int streamed = g_streamed_mode.load(std::memory_order_relaxed);
     std::string key(reinterpret_cast<const char *>(&p), sizeof p);
     key.append(reinterpret_cast<const char *>(&tile), sizeof tile);
     key.append(reinterpret_cast<const char *>(&f_a), sizeof f_a);
     key.append(reinterpret_cast<const char *>(&f_b), sizeof f_b);
     key.append(reinterpret_cast<const char *>(&dev), sizeof dev);
     key.append(reinterpret_cast<const char *>(&nsteps), sizeof nsteps);
+    key.append(reinterpret_cast<const char *>(&streamed), sizeof streamed);
+    std::shared_ptr<GraphEntry> evicted;  // destroyed after the lock is released
     std::lock_guard<std::mutex> lock(g_graph_mu);
     auto it = g_graphs.find(key);
     if (it != g_graphs.end()) {
-        *out = it->second.exec;
+        it->second->used = ++g_graph_clock;
+        *out = it->second;
         return PRC_OK;
     }
-    if (g_graphs.size() >= kGraphCacheMax) destroy_graphs_locked();
+    if (g_graphs.size() >= kGraphCacheMax) {
+        auto lru = g_graphs.begin();
+        for (auto j = g_graphs.begin(); j != g_graphs.end(); ++j)
+            if (j->second->used < lru->second->used) lru = j;
+        evicted = std::move(lru->second);
+        g_graphs.erase(lru);
+    }
     hipStream_t cs = nullptr;
     HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     prc_status st = PRC_OK;
@@ -251,8 +273,13 @@ static prc_status get_graph(const prc_params &p, int tile, void *f_a, void *f_b,
             hipGraphExec_t x = nullptr;
             e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
             if (e == hipSuccess) {
-                g_graphs.emplace(key, GraphEntry{g, x});
-                *out = x;
+                auto entry = std::make_shared<GraphEntry>();
+                entry->graph = g;
+                entry->exec = x;
+                entry->dev = dev;
+                entry->used = ++g_graph_clock;
+                g_graphs.emplace(key, entry);
+                *out = std::move(entry);
             } else {
                 (void)hipGraphDestroy(g);
             }
@@ -349,6 +376,9 @@ prc_status prc_step(const prc_params *p, void *f_a, void *f_b, int64_t nsteps, h
     if ((st = check_buf(f_a, "f_a")) != PRC_OK || (st = check_buf(f_b, "f_b")) != PRC_OK) return st;
     if (f_a == f_b) return fail(PRC_EINVAL, "f_a and f_b must be distinct buffers");
     if (nsteps < 0) return fail(PRC_EINVAL, "nsteps < 0");
+    // an earlier resident launch on this device that lost a wait is reported
+    // here, before anything builds on its state
+    if ((st = resident_report()) != PRC_OK) return st;
     int64_t k = 0;
     const int tile = tile_choice(*p);
     if (tile == kResidentTile && (st = resident_prepare(stream)) != PRC_OK) return st;
@@ -362,9 +392,9 @@ prc_status prc_step(const prc_params *p, void *f_a, void *f_b, int64_t nsteps, h
     // (the resident sweep takes any number of steps in one launch: no graph)
     if (tile != kResidentTile && gsteps > 0 && cap == hipStreamCaptureStatusNone &&
         nsteps >= 2 * gsteps) {
-        hipGraphExec_t exec = nullptr;
-        if ((st = get_graph(*p, tile, f_a, f_b, gsteps, &exec)) != PRC_OK) return st;
-        for (; k + gsteps <= nsteps; k += gsteps) HIP_TRY(hipGraphLaunch(exec, stream));
+        std::shared_ptr<GraphEntry> g;  // held while replaying
+        if ((st = get_graph(*p, tile, f_a, f_b, gsteps, &g)) != PRC_OK) return st;
+        for (; k + gsteps <= nsteps; k += gsteps) HIP_TRY(hipGraphLaunch(g->exec, stream));
     }
     return run_steps(*p, tile, f_a, f_b, k, nsteps - k, stream);
 }
@@ -382,7 +412,7 @@ prc_status prc_residual(const prc_params *p, const void *f, double *u_prev, void
     HIP_TRY(hipMemcpyAsync(out, sc + 4 * kRedMaxBlocks, 4 * sizeof(double),
                            hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
-    if ((st = resident_check(stream)) != PRC_OK) return st;
+    if ((st = resident_report()) != PRC_OK) return st;
     out[2] += p->rho0 * (double)p->nx * (double)p->ny;  // rest part of the mass
     return PRC_OK;
 }
@@ -393,6 +423,7 @@ prc_status prc_macros(const prc_params *p, const void *f, double *rho, double *u
     prc_status st = validate(p);
     if (st != PRC_OK) return st;
     if ((st = check_buf(f, "f")) != PRC_OK) return st;
+    if ((st = resident_report()) != PRC_OK) return st;
     return PRC_DISPATCH(*p, launch_macros, *p, f, rho, ux, uy, stream);
 }
 
@@ -436,6 +467,7 @@ prc_status prc_solve(const prc_params *p, void *f_a, void *f_b, double *u_prev, 
         if ((st = prc_step(p, cur, oth, max_steps - n, stream)) != PRC_OK) return st;
         n = max_steps;
         HIP_TRY(hipStreamSynchronize(stream));
+        if ((st = resident_report()) != PRC_OK) return st;
     }
     *steps_out = n;
     if (hist_len) *hist_len = nh;
@@ -472,7 +504,7 @@ prc_status prc_tune(const prc_params *p, int32_t *tile_out, hipStream_t stream)
         float ms = 0.0f;
         if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
         // a resident launch that lost a wait does not count
-        if (he == hipSuccess && t == kResidentTile && resident_check(stream) != PRC_OK) continue;
+        if (he == hipSuccess && t == kResidentTile && resident_report() != PRC_OK) continue;
         ms /= (float)(t == kResidentTile ? kResidentTuneSteps : kTiles[t].steps);  // per step
         if (he == hipSuccess && (best < 0 || ms < best_ms)) {
             best = t;
@@ -518,8 +550,25 @@ prc_status prc_set_tile(const prc_params *p, int32_t tile)
 
 prc_status prc_release_graphs(void)
 {
-    std::lock_guard<std::mutex> lock(g_graph_mu);
-    destroy_graphs_locked();
+    decltype(g_graphs) old;  // destroyed (after their devices finish) outside the lock
+    {
+        std::lock_guard<std::mutex> lock(g_graph_mu);
+        old.swap(g_graphs);
+    }
+    old.clear();
+    return PRC_OK;
+}
+
+prc_status prc_release_resident(void) { return resident_release(); }
+
+prc_status prc_resident_status(void) { return resident_report(); }
+
+prc_status prc_set_resident_wait(int64_t ticks) { return resident_set_wait(ticks); }
+
+prc_status prc_set_streamed(int32_t mode)
+{
+    if (mode < -1 || mode > 1) return fail(PRC_EINVAL, "streamed mode %d not in {-1, 0, 1}", mode);
+    g_streamed_mode.store(mode, std::memory_order_relaxed);
     return PRC_OK;
 }
 

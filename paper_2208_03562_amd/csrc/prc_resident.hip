@@ -1,8 +1,10 @@
 // Host side of the resident sweep (k_resident, prc_resident.hpp): which
-// problems it can run, the per-device synchronisation block, the launches and
-// the report of an aborted wait.
+// problems it can run, the per-device synchronisation block, the launches
+// (serialised across streams), the report of an aborted wait, and the
+// release of the per-device resources.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <mutex>
 #include <utility>
 
@@ -22,11 +24,25 @@ constexpr int64_t kResidentMaxSteps = 1 << 16;
 struct ResidentDevice {
     ResidentSync *sync = nullptr;
     void *xch = nullptr;  // exchange blocks: two parities of every subdomain, tagged
+    // pinned host word a timed-out wait sets (read without synchronising)
+    volatile uint64_t *mailbox = nullptr;
+    // completion of the latest resident launch on this device, and its stream:
+    // a launch on another stream waits for it, so that two launches never
+    // share the exchange buffer and the compute units at once
+    hipEvent_t last = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool has_last = false;
     int cus = 0;  // compute units
     int lds = 0;  // LDS a workgroup may use, bytes
 };
 std::mutex g_res_mu;
 ResidentDevice g_res[kMaxDevices];
+// whether any device has its resident buffers (reports need no device query
+// in a process that never ran the resident sweep)
+std::atomic<int> g_res_devices{0};
+// how long a workgroup waits for a neighbour's value before it gives up, in
+// ticks of the 100 MHz real-time clock (prc_set_resident_wait)
+std::atomic<uint64_t> g_wait_ticks{kResidentWaitTicks};
 
 prc_status current_device(ResidentDevice **out)
 {
@@ -67,12 +83,13 @@ prc_status launch_res(const prc_params &p, const void *src, void *dst, int nstep
     c.tiles_y = (p.ny + kResidentSY - 1) / kResidentSY;
     c.tiles_per_xcd = (c.tiles_x * c.tiles_y + kXcds - 1) / kXcds;
     const dim3 grid(c.tiles_per_xcd * kXcds), block(kResidentThreads);
+    const uint64_t wait = g_wait_ticks.load(std::memory_order_relaxed);
     if (is_plain_method(p))
         hipLaunchKernelGGL((k_resident<ST, BC, false, true>), grid, block, 0, s, (ST *)src,
-                           (ST *)dst, d.xch, c, d.sync, nsteps);
+                           (ST *)dst, d.xch, c, d.sync, (uint64_t *)d.mailbox, wait, nsteps);
     else
         hipLaunchKernelGGL((k_resident<ST, BC, true, false>), grid, block, 0, s, (ST *)src,
-                           (ST *)dst, d.xch, c, d.sync, nsteps);
+                           (ST *)dst, d.xch, c, d.sync, (uint64_t *)d.mailbox, wait, nsteps);
     HIP_TRY(hipGetLastError());
     return PRC_OK;
     }
@@ -105,20 +122,30 @@ prc_status resident_prepare(hipStream_t s)
     if (cap != hipStreamCaptureStatusNone)
         return fail(PRC_EHIP, "resident sweep: its flags are set up by the first call on a "
                               "device, which must not be under graph capture");
-    void *m = nullptr, *x = nullptr;
+    void *m = nullptr, *x = nullptr, *h = nullptr;
+    hipEvent_t ev = nullptr;
     const size_t xbytes = (size_t)2 * kResidentMaxGroups * kXchElems * kXchPair;
     hipError_t e = hipMalloc(&m, sizeof(ResidentSync));
     if (e == hipSuccess) e = hipMalloc(&x, xbytes);
+    if (e == hipSuccess) e = hipHostMalloc(&h, sizeof(uint64_t), hipHostMallocMapped | hipHostMallocCoherent);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipMemset(m, 0, sizeof(ResidentSync));
     if (e == hipSuccess) e = hipMemset(x, 0, xbytes);  // every tag 0: no step yet
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         if (m) (void)hipFree(m);
         if (x) (void)hipFree(x);
+        if (h) (void)hipHostFree(h);
+        if (ev) (void)hipEventDestroy(ev);
         return fail(PRC_EHIP, "resident sweep: setting up its flags: %s", hipGetErrorString(e));
     }
+    *(volatile uint64_t *)h = 0;
     d->sync = (ResidentSync *)m;
     d->xch = x;
+    d->mailbox = (volatile uint64_t *)h;
+    d->last = ev;
+    d->has_last = false;
+    g_res_devices.fetch_add(1);
     return PRC_OK;
 }
 
@@ -131,7 +158,14 @@ prc_status launch_resident(const prc_params &p, const void *src, void *dst, int6
     ResidentDevice *d = nullptr;
     prc_status st = current_device(&d);
     if (st != PRC_OK) return st;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(s, &cap));
+    std::lock_guard<std::mutex> lock(g_res_mu);
     if (!d->sync) return fail(PRC_EHIP, "resident sweep: flags not set up on this device");
+    // a launch on another stream than the latest one waits for that one
+    // (launches captured into a graph are ordered by whoever replays it)
+    const bool track = cap == hipStreamCaptureStatusNone;
+    if (track && d->has_last && d->last_stream != s) HIP_TRY(hipStreamWaitEvent(s, d->last, 0));
     void *a = const_cast<void *>(src), *b = dst;
     while (nsteps > 0 && st == PRC_OK) {
         const int64_t n = nsteps < kResidentMaxSteps ? nsteps : kResidentMaxSteps;
@@ -139,22 +173,60 @@ prc_status launch_resident(const prc_params &p, const void *src, void *dst, int6
         if (n & 1) std::swap(a, b);  // an odd count leaves the state in the second buffer
         nsteps -= n;
     }
+    if (track && st == PRC_OK) {
+        HIP_TRY(hipEventRecord(d->last, s));
+        d->has_last = true;
+        d->last_stream = s;
+    }
     return st;
 }
 
-prc_status resident_check(hipStream_t s)
+prc_status resident_report()
 {
+    if (g_res_devices.load() == 0) return PRC_OK;
     ResidentDevice *d = nullptr;
     prc_status st = current_device(&d);
-    if (st != PRC_OK || !d->sync) return st;
-    uint64_t abort = 0;
-    HIP_TRY(hipMemcpyAsync(&abort, &d->sync->abort, sizeof abort, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (abort == 0) return PRC_OK;
-    HIP_TRY(hipMemsetAsync(&d->sync->abort, 0, sizeof abort, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    return fail(PRC_EHIP, "resident sweep: a workgroup waited in vain for a neighbour (not every "
-                          "subdomain had a compute unit); the state is invalid");
+    if (st != PRC_OK || !d->mailbox) return st;
+    if (*d->mailbox == 0) return PRC_OK;
+    *d->mailbox = 0;
+    return fail(PRC_EHIP, "resident sweep: a workgroup of an earlier launch on this device waited "
+                          "in vain for a neighbour (not every subdomain had a compute unit at "
+                          "once); the state it produced is invalid");
 }
 
+prc_status resident_release()
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(PRC_EHIP, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_res_mu);
+    ResidentDevice &d = g_res[dev];
+    if (!d.sync) return PRC_OK;
+    HIP_TRY(hipDeviceSynchronize());  // no launch may still use them
+    hipError_t e = hipFree(d.sync);
+    if (hipFree(d.xch) != hipSuccess && e == hipSuccess) e = hipErrorInvalidValue;
+    if (hipHostFree((void *)d.mailbox) != hipSuccess && e == hipSuccess) e = hipErrorInvalidValue;
+    if (hipEventDestroy(d.last) != hipSuccess && e == hipSuccess) e = hipErrorInvalidValue;
+    d.sync = nullptr;
+    d.xch = nullptr;
+    d.mailbox = nullptr;
+    d.last = nullptr;
+    d.has_last = false;
+    d.last_stream = nullptr;
+    g_res_devices.fetch_sub(1);
+    if (e != hipSuccess)
+        return fail(PRC_EHIP, "resident sweep: releasing its buffers: %s", hipGetErrorString(e));
+    return PRC_OK;
+}
+
+}  // namespace prc
+
+namespace prc {
+prc_status resident_set_wait(int64_t ticks)
+{
+    if (ticks < -1) return fail(PRC_EINVAL, "wait %lld ticks: need >= 0, or -1 for the default",
+                                (long long)ticks);
+    g_wait_ticks.store(ticks < 0 ? kResidentWaitTicks : (uint64_t)ticks, std::memory_order_relaxed);
+    return PRC_OK;
+}
 }  // namespace prc

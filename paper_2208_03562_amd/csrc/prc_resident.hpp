@@ -29,7 +29,9 @@
 // LDS of a subdomain leaves no room for a second), at most as many
 // subdomains as CUs.  Waits are bounded: a value that does not arrive within
 // about half a second (a workgroup that never got a CU) sets an abort word
-// that ends every other wait; the host reports it.
+// that ends every other wait of the launch, and a word in host memory that
+// the host reads without synchronising; the launch's last workgroup clears
+// the abort word, so the next launch starts clean.
 #pragma once
 
 #include "prc_sweep2.hpp"
@@ -39,7 +41,7 @@ namespace prc {
 constexpr int kResidentSX = 64, kResidentSY = 32;  // subdomain, nodes
 constexpr int kResidentThreads = 1024;              // two nodes per thread
 constexpr int kResidentMaxGroups = 512;
-constexpr uint64_t kResidentWaitTicks = 1ull << 26;  // ~0.67 s of the 100 MHz clock
+constexpr uint64_t kResidentWaitTicks = 1ull << 26;  // default wait: ~0.67 s of the 100 MHz clock
 // Step tags are 32-bit: the step counter restarts from zero (and the exchange
 // buffer is cleared) before it reaches this.
 constexpr uint64_t kResidentStepLimit = 1ull << 31;
@@ -58,7 +60,7 @@ constexpr int kAgent = 16;
 struct ResidentSync {
     uint64_t step;   // steps run by earlier resident launches: the tags' base
     uint64_t done;   // workgroups finished in the current launch
-    uint64_t abort;  // a wait timed out (set by the device, cleared by the host)
+    uint64_t abort;  // a wait of the current launch timed out (cleared by its last workgroup)
 };
 
 __device__ __forceinline__ uint64_t ld_agent(uint64_t *p)
@@ -151,7 +153,8 @@ __device__ __forceinline__ void reflect(const Coef<CT> &c, ST (*P)[SY + 4][SX + 
 template <typename ST, int BC, bool FORCE, bool ALL>
 __global__ void __launch_bounds__(kResidentThreads)
     k_resident(ST *__restrict__ buf0, ST *__restrict__ buf1, void *__restrict__ xch,
-               const Coef<typename Mem<ST>::CT> c, ResidentSync *__restrict__ sy, int nsteps)
+               const Coef<typename Mem<ST>::CT> c, ResidentSync *__restrict__ sy,
+               uint64_t *__restrict__ mailbox, uint64_t wait_ticks, int nsteps)
 {
     using CT = typename Mem<ST>::CT;
     constexpr int SX = kResidentSX, SY = kResidentSY, T = kResidentThreads;
@@ -338,8 +341,11 @@ __global__ void __launch_bounds__(kResidentThreads)
                         s_abort = 1;
                         break;
                     }
-                    if (__builtin_amdgcn_s_memrealtime() - t0 > kResidentWaitTicks) {
+                    if (__builtin_amdgcn_s_memrealtime() - t0 > wait_ticks) {
                         st_agent(&sy->abort, 1);
+                        // host-visible report (pinned host memory, system scope)
+                        __hip_atomic_store(mailbox, (uint64_t)1, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_SYSTEM);
                         s_abort = 1;
                         break;
                     }
@@ -424,9 +430,10 @@ __global__ void __launch_bounds__(kResidentThreads)
     }
 
     // The last workgroup to finish advances the tags' base for the next
-    // launch; near the end of the 32-bit tags it clears the exchange buffer
-    // (no other workgroup of this launch touches it any more) and restarts
-    // the count, so no old tag can match a new step.
+    // launch and clears the abort word (no wait of this launch is left);
+    // near the end of the 32-bit tags it clears the exchange buffer (no other
+    // workgroup of this launch touches it any more) and restarts the count,
+    // so no old tag can match a new step.
     if (t == 0) {
         const uint64_t old =
             __hip_atomic_fetch_add(&sy->done, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -444,6 +451,7 @@ __global__ void __launch_bounds__(kResidentThreads)
         }
         if (t == 0) {
             st_agent(&sy->done, 0);
+            st_agent(&sy->abort, 0);
             st_agent(&sy->step, next >= kResidentStepLimit ? 0 : next);
         }
     }

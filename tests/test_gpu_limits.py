@@ -58,6 +58,39 @@ def test_4096x2048_f64_two_step_launches_every_node(O):
     assert err < 1e-12, err
 
 
+@pytest.mark.parametrize("storage,tile", [("f16", 7), ("bf16", 7), ("f32", 7), ("f32", 8)])
+def test_4096x2048_streamed_two_step_every_node(O, storage, tile):
+    """The full-size shallow cavity as the benchmark runs its 16-bit and FP32
+    rows: two-step launches on 1024-thread tiles, in the instance for states
+    streamed from HBM (both states exceed 160 MB), four steps from a seeded
+    random state.  Bit for bit the single-step sweep, and against the oracle
+    at every node within four one-step bounds."""
+    w = workloads.CAVITY_4096x2048_MA002[storage]
+    s = spec(w.nx, w.ny, w.r, w.gamma, re=w.re, omega_nu=None, u_lid=w.u_lid, storage=storage)
+    from paper_2208_03562_amd import capi, solver
+    noise = ROUND[storage](workloads.deviation_noise(w.nx, w.ny, seed=4098, amplitude=1e-3))
+    p = lib_params(s)
+    assert 2 * capi.prc_state_bytes(p) > 160 * 2 ** 20
+    out = {}
+    for t in (0, tile):
+        sol = solver.Solver(p)
+        capi.prc_set_tile(sol.p, t)
+        sol.set_state(noise)
+        sol.step(4)
+        out[t] = sol.get_state().cpu().numpy()
+        capi.prc_set_tile(sol.p, -1)
+        del sol
+        torch.cuda.empty_cache()
+    assert bool((out[tile] == out[0]).all())
+    po = oracle_params(O, s)
+    ft = np.ascontiguousarray(O.rest_state(po) + noise)
+    del noise
+    O.step(po, ft, 4)
+    dev = oracle_deviation(O, po, ft)
+    err = np.abs(out[tile] - dev).max() / np.abs(dev).max()
+    assert err < 4 * ONE_STEP_BOUND[storage], err
+
+
 def test_largest_state_corners_match_a_small_cavity(O):
     """The largest FP32 state (16384 x ny_max nodes, just under 4 GiB): after
     k steps from rest a node depends only on nodes within 2k of it (one link

@@ -124,3 +124,65 @@ def test_resident_steps_captured_by_the_caller():
     finally:
         capi.prc_set_tile(p, -1)
         capi.prc_release_graphs()
+
+
+def test_resident_calls_on_two_streams_give_the_single_step_bits():
+    """Two problems on two streams issue resident calls back to back with no
+    synchronisation between them: the library orders resident launches on one
+    device (a launch on another stream waits for the latest one), so each
+    problem gets the single-step bits and no launch loses a wait."""
+    from paper_2208_03562_amd import capi, solver
+    specs = [spec(200, 90, 2.0, 0.5, omega_nu=1.3, u_lid=0.05, storage="f32"),
+             spec(256, 128, 0.5, 0.2, omega_nu=1.1, u_lid=0.02, storage="f32")]
+    counts = [[3, 8, 1, 12], [5, 2, 9, 4]]
+    ref = [run(s, 0, sum(c), seed=20 + k) for k, (s, c) in enumerate(zip(specs, counts))]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    sols = []
+    for k, s in enumerate(specs):
+        sol = solver.Solver(lib_params(s), stream=streams[k])
+        capi.prc_set_tile(sol.p, RESIDENT)
+        sol.set_state(workloads.deviation_noise(s["nx"], s["ny"], 20 + k, 1e-3))
+        sols.append(sol)
+    torch.cuda.synchronize()
+    for i in range(4):
+        for k in range(2):
+            sols[k].step(counts[k][i])
+    torch.cuda.synchronize()
+    capi.prc_resident_status()  # raises if a launch lost a wait
+    for k in range(2):
+        assert bool((sols[k].get_state() == ref[k]).all()), k
+        capi.prc_set_tile(sols[k].p, -1)
+
+
+def test_lost_wait_is_reported_once_and_the_next_launch_is_clean():
+    """A wait limit of zero ticks makes the first value that is not there yet
+    end the launch (every workgroup still finishes normally).  The failure is
+    reported once -- by prc_resident_status here -- and the next launch,
+    with the default limit, gives the single-step bits again."""
+    from paper_2208_03562_amd import capi, solver
+    w = workloads.CAVITY_1024x512_F32
+    s = spec(w.nx, w.ny, w.r, w.gamma, re=w.re, omega_nu=None, u_lid=w.u_lid, storage="f32")
+    sol = solver.Solver(lib_params(s))
+    capi.prc_set_tile(sol.p, RESIDENT)
+    capi.prc_resident_status()  # nothing pending
+    capi.prc_set_resident_wait(0)
+    try:
+        sol.step(2000)
+        torch.cuda.synchronize()
+    finally:
+        capi.prc_set_resident_wait(-1)
+    try:
+        capi.prc_resident_status()
+        lost = False
+    except capi.PrcError as e:
+        assert e.status == capi.PRC_EHIP
+        lost = True
+    capi.prc_resident_status()  # reported once, then clear
+    if not lost:
+        capi.prc_set_tile(sol.p, -1)
+        pytest.skip("no value arrived late in 2000 steps: nothing to report")
+    # a clean launch from a fresh state
+    small = spec(200, 90, 2.0, 0.5, omega_nu=1.3, u_lid=0.05, storage="f32")
+    ref = run(small, 0, 7, seed=31)
+    assert bool((run(small, RESIDENT, 7, seed=31) == ref).all())
+    capi.prc_set_tile(sol.p, -1)

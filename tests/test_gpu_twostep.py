@@ -55,3 +55,24 @@ def test_two_step_graph_replays():
     ref = run(s, 1, 136, seed=9)
     for tile in TWO_STEP_TILES:
         assert bool((run(s, tile, 136, seed=9) == ref).all()), tile
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
+@pytest.mark.parametrize("case", CASES[:3], ids=lambda c: f"{c[0]}-r{c[1]}-g{c[2]}")
+def test_streamed_instance_gives_the_single_step_bits(storage, case):
+    """The 1024-thread two-step tiles have an instance for states streamed
+    from HBM (chosen by size); forced on small ragged grids it must give the
+    single-step bits too."""
+    from paper_2208_03562_amd import capi
+    bc, r, gamma, extra = case
+    for nx, ny in ((150, 37), (130, 260)):
+        s = spec(nx, ny, r, gamma, omega_nu=1.3, bc=bc, storage=storage, **extra)
+        ref = run(s, 0, 7, seed=nx + ny)
+        capi.prc_set_streamed(1)
+        try:
+            for tile in (7, 8):
+                got = run(s, tile, 7, seed=nx + ny)
+                assert bool((got == ref).all()), (tile, nx, ny)
+        finally:
+            capi.prc_set_streamed(-1)
+            capi.prc_release_graphs()
