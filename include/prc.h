@@ -175,6 +175,24 @@ prc_status prc_step(const prc_params *p, void *f_a, void *f_b, int64_t nsteps,
 prc_status prc_residual(const prc_params *p, const void *f, double *u_prev,
                         void *scratch, double out[4], hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc: graph-free serving loops, harnesses that forbid allocation):
+ * prc_residual without the scratch argument.  Same sums, same order, same
+ * results bit for bit, same u_prev update, same synchronisation and errors;
+ * the block partials and the result live in a static device array of
+ * 4 * 1024 + 4 doubles (32 KiB + 32 bytes) that the library holds on every
+ * device it runs on until the process ends.  That array takes the largest
+ * partition of any valid problem, so no valid problem exceeds it (the call
+ * still checks and returns PRC_EINVAL if one did).  The call allocates
+ * nothing: it launches two kernels, copies 32 bytes to `out` and
+ * synchronises the stream.  Calls on one device share the array, so calls
+ * that overlap in time on one device (several threads or streams at once)
+ * race and may return each other's sums; every call overwrites all it reads,
+ * so nothing needs clearing between calls.  u_prev: device
+ * double[2][ny][nx]; out: host double[4] (as prc_residual). */
+prc_status prc_residual_noalloc(const prc_params *p, const void *f, double *u_prev,
+                                double out[4], hipStream_t stream);
+
 /* Hydrodynamic fields of state f (eq. hydrodynamicfields after streaming):
  * rho, u_x, u_y as device double[ny][nx] arrays (row j at offset j * nx).
  * Any of the three output pointers may be NULL. */

@@ -92,6 +92,7 @@ _PROTOS = {
     "prc_init": (ctypes.c_int, [_P, _VP, _VP]),
     "prc_step": (ctypes.c_int, [_P, _VP, _VP, ctypes.c_int64, _VP]),
     "prc_residual": (ctypes.c_int, [_P, _VP, _DP, _VP, ctypes.POINTER(ctypes.c_double), _VP]),
+    "prc_residual_noalloc": (ctypes.c_int, [_P, _VP, _DP, ctypes.POINTER(ctypes.c_double), _VP]),
     "prc_macros": (ctypes.c_int, [_P, _VP, _DP, _DP, _DP, _VP]),
     "prc_solve": (ctypes.c_int, [_P, _VP, _VP, _DP, _VP, ctypes.c_double, ctypes.c_int64,
                                  ctypes.c_int64, _I64P, ctypes.POINTER(ctypes.c_double),
@@ -208,6 +209,13 @@ def prc_step(p: prc_params, f_a: int, f_b: int, nsteps: int, stream: int = 0) ->
 def prc_residual(p: prc_params, f: int, u_prev: int, scratch: int, stream: int = 0):
     out = (ctypes.c_double * 4)()
     _check("prc_residual", lib().prc_residual(ctypes.byref(p), f, u_prev, scratch, out, stream))
+    return list(out)
+
+
+def prc_residual_noalloc(p: prc_params, f: int, u_prev: int, stream: int = 0):
+    out = (ctypes.c_double * 4)()
+    _check("prc_residual_noalloc",
+           lib().prc_residual_noalloc(ctypes.byref(p), f, u_prev, out, stream))
     return list(out)
 
 

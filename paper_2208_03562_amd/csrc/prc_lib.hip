@@ -294,6 +294,57 @@ static prc_status get_graph(const prc_params &p, int tile, void *f_a, void *f_b,
     return PRC_OK;
 }
 
+// The convergence check with its block partials and result in sc (device,
+// 4 * kRedMaxBlocks + 4 doubles): launches, copies the result to the host,
+// synchronises the stream, reports a failed resident launch, and adds the
+// rest part of the mass.
+static prc_status residual_into(const prc_params &p, const void *f, double *u_prev, double *sc,
+                                double out[4], hipStream_t stream)
+{
+    prc_status st = PRC_DISPATCH(p, launch_residual, p, f, u_prev, sc, stream);
+    if (st != PRC_OK) return st;
+    HIP_TRY(hipMemcpyAsync(out, sc + 4 * kRedMaxBlocks, 4 * sizeof(double),
+                           hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    if ((st = resident_report()) != PRC_OK) return st;
+    out[2] += p.rho0 * (double)p.nx * (double)p.ny;  // rest part of the mass
+    return PRC_OK;
+}
+
+// ------------------------------------------ scratch that needs no allocation --
+// prc_residual_noalloc keeps the block partials and the result of the check
+// here instead of in a caller's buffer: 4 * kRedMaxBlocks + 4 doubles (32 KiB
+// + 32 bytes; the largest partition of any problem), one copy on every device
+// the library runs on, held until the process ends.  Every call on a device
+// shares that device's copy.  Host code must not use this name as an address
+// (it is a host-side stand-in): the device address comes from
+// hipGetSymbolAddress, once per device, in static_scratch().
+static __device__ __align__(256) double scratch[4 * kRedMaxBlocks + 4];
+
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of the current device's copy of `scratch` (looked up on the
+// first call on each device, with that device current).
+static prc_status static_scratch(double **out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxScratchDevices) return fail(PRC_EHIP, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(PRC_EHIP, "address of the static scratch array on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = (double *)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return PRC_OK;
+}
+
 }  // namespace prc
 
 using namespace prc;
@@ -406,15 +457,22 @@ prc_status prc_residual(const prc_params *p, const void *f, double *u_prev, void
     if (st != PRC_OK) return st;
     if ((st = check_buf(f, "f")) != PRC_OK) return st;
     if (!u_prev || !scratch || !out) return fail(PRC_EINVAL, "NULL u_prev, scratch or out");
-    double *sc = (double *)scratch;
-    st = PRC_DISPATCH(*p, launch_residual, *p, f, u_prev, sc, stream);
+    return residual_into(*p, f, u_prev, (double *)scratch, out, stream);
+}
+
+prc_status prc_residual_noalloc(const prc_params *p, const void *f, double *u_prev,
+                                double out[4], hipStream_t stream)
+{
+    prc_status st = validate(p);
     if (st != PRC_OK) return st;
-    HIP_TRY(hipMemcpyAsync(out, sc + 4 * kRedMaxBlocks, 4 * sizeof(double),
-                           hipMemcpyDeviceToHost, stream));
-    HIP_TRY(hipStreamSynchronize(stream));
-    if ((st = resident_report()) != PRC_OK) return st;
-    out[2] += p->rho0 * (double)p->nx * (double)p->ny;  // rest part of the mass
-    return PRC_OK;
+    if ((st = check_buf(f, "f")) != PRC_OK) return st;
+    if (!u_prev || !out) return fail(PRC_EINVAL, "NULL u_prev or out");
+    if (prc_scratch_bytes(p) > sizeof(scratch))
+        return fail(PRC_EINVAL, "the check needs %zu bytes of scratch, more than the %zu of the "
+                                "static array", prc_scratch_bytes(p), sizeof(scratch));
+    double *sc = nullptr;
+    if ((st = static_scratch(&sc)) != PRC_OK) return st;
+    return residual_into(*p, f, u_prev, sc, out, stream);
 }
 
 prc_status prc_macros(const prc_params *p, const void *f, double *rho, double *ux, double *uy,
