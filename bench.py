@@ -61,21 +61,25 @@ def run_gpu(w: workloads.Cavity, steps: int, warmup: int):
             R = rel_residual(out)
             if diverged_at is None and not (math.isfinite(R) and out[3] < 1.0):
                 diverged_at = done
-    torch.cuda.synchronize()
     log(f"[bench] {w.name}: warmup {warmup} steps done")
 
-    ev = []
+    # one pair of HIP events per chunk of at most CHECK_EVERY steps, on the
+    # solver's stream; created and recorded once before the timed region (a
+    # torch event creates its HIP event at its first record)
+    chunks = [min(CHECK_EVERY, steps - k) for k in range(0, steps, CHECK_EVERY)]
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in chunks]
+    for a, b in ev:
+        a.record(stream)
+        b.record(stream)
     hist = []
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     done = 0
-    while done < steps:
-        n = min(CHECK_EVERY, steps - done)
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
+    for (a, b), n in zip(ev, chunks):
         a.record(stream)
         sol.step(n)
         b.record(stream)
-        ev.append((a, b, n))
         done += n
         if done % CHECK_EVERY == 0:
             out = sol.residual()  # synchronises the stream
@@ -83,18 +87,27 @@ def run_gpu(w: workloads.Cavity, steps: int, warmup: int):
             hist.append(R)
             if diverged_at is None and not (math.isfinite(R) and out[3] < 1.0):
                 diverged_at = warmup + done
-    stream.synchronize()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    sweep_ms = sum(a.elapsed_time(b) for a, b, _ in ev)
-    sweep_n = sum(n for _, _, n in ev)
+    # a resident launch that lost a wait would have produced an invalid state
+    try:
+        capi.prc_resident_status()
+        resident_ok = True
+    except capi.PrcError:
+        resident_ok = False
+    chunk_ms = [a.elapsed_time(b) for a, b in ev]
     nodes = w.nx * w.ny
     wall = t1 - t0
+    full = [m for m, n in zip(chunk_ms, chunks) if n == chunks[0]]
     res = dict(
         wall_s=wall,
         mlups=nodes * steps / wall / 1e6,
         ms_per_step=wall * 1e3 / steps,
-        sweep_us=sweep_ms * 1e3 / sweep_n,
+        sweep_us=sum(chunk_ms) * 1e3 / steps,
+        # the first chunk's size and the mean event time of the chunks of that size
+        chunk_steps=chunks[0],
+        chunk_us=1e3 * sum(full) / len(full),
+        resident_ok=resident_ok,
         residual_last=(hist[-1] if math.isfinite(hist[-1]) else str(hist[-1])) if hist else None,
         diverged_at=diverged_at,
     )
@@ -218,10 +231,39 @@ def run_serve(n_req: int, solo_req: int, mlups_hint: float):
     }
 
 
-def run_cpu_baseline(w: workloads.Cavity, budget_s: float):
-    import numpy as np  # noqa: F401
-    from oracle import oracle as O
+def native_oracle():
+    """The oracle's C source compiled for the host that runs the benchmark
+    (gcc -O3 -march=native -fopenmp: the CPU baseline's build; the source is
+    the oracle as it stands) into a temporary folder, loaded through a fresh
+    copy of its ctypes wrapper."""
+    import importlib.util
+    import subprocess
+    import tempfile
+    d = tempfile.mkdtemp(prefix="orc_native_")
+    so = os.path.join(d, "liborc.so")
+    subprocess.run(["gcc", "-O3", "-march=native", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+                    "-o", so, os.path.join(ROOT, "oracle", "prc_oracle.c"), "-lm"], check=True)
+    spec = importlib.util.spec_from_file_location("oracle_native",
+                                                  os.path.join(ROOT, "oracle", "oracle.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    mod.LIB = so
+    mod._lib = None
+    return mod
 
+
+def host_cpu() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def run_cpu_baseline(w: workloads.Cavity, budget_s: float):
+    O = native_oracle()
     po = O.with_re(O.params(w.nx, w.ny, w.r, w.gamma, 1.0, u_lid=w.u_lid), w.re)
     ft = O.rest_state(po)
     t0 = time.perf_counter()
@@ -246,18 +288,37 @@ def run_cpu_baseline(w: workloads.Cavity, budget_s: float):
     return dict(value=w.nx * w.ny * n / dt / 1e6, unit="MLUPS", cores=cores,
                 kind="oracle",
                 sample=f"{n} FP64 steps of the {w.nx}x{w.ny} cavity from rest "
-                       f"(after 1 untimed step), OpenMP over rows",
+                       f"(after 1 untimed step), OpenMP over rows, gcc -O3 -march=native",
+                host_cpu=host_cpu(), host_threads=os.cpu_count(),
                 one_thread=dict(value=w.nx * w.ny * n1 / dt1 / 1e6, unit="MLUPS", cores=1,
                                 sample=f"{n1} further FP64 steps of the same run"))
 
 
+PMC_COPY_BYTES = 256 * 2 ** 20  # bytes read and bytes written by pmc_run's copy
+# grids whose sweep instances the counter runs cover: the benchmark's
+# 1024 x 512 FP32 cavity and the 4096 x 2048 grids of every storage
+PMC_SMALL = workloads.CAVITY_1024x512_F32
+PMC_BIG = (workloads.CAVITY_4096x2048_F32, workloads.CAVITY_4096x2048_MA002["f16"],
+           workloads.CAVITY_4096x2048_MA002["bf16"], workloads.CAVITY_4096x2048_MA002["f64"])
+# resident launches of the driver's timed call (20 steps), counted first
+PMC_SHORT_STEPS, PMC_SHORT_LAUNCHES = 20, 5
+RESIDENT_TILE = 9
+
+
+def grid_key(nx: int, ny: int, storage: str) -> str:
+    return f"{nx}x{ny}_{storage}"
+
+
 def pmc_run(steps: int):
-    """Short fixed workload for hardware-counter runs: a plain device copy of
-    256 MiB each way (the reference for scaling byte counters), then `steps`
-    steps of the 1024x512 FP32 cavity (one launch of the resident sweep when
-    the tuner picks it) and min(steps, 64) of the 4096x2048 one."""
+    """Fixed workload of the counter runs: a plain device copy of 256 MiB
+    each way (the reference for scaling byte counters); on the 1024 x 512
+    FP32 cavity PMC_SHORT_LAUNCHES resident launches of PMC_SHORT_STEPS steps
+    (the launch the driver's `--steps 20` call times) and then the tuner,
+    which launches every sweep instance (the resident sweep in 1000-step
+    launches); on each 4096 x 2048 grid the tuner.  `steps` is unused (kept
+    for the command line)."""
     import torch
-    from paper_2208_03562_amd import solver
+    from paper_2208_03562_amd import capi, solver
 
     n = 256 * 2 ** 20 // 4
     a = torch.ones(n, device="cuda:0")
@@ -266,17 +327,26 @@ def pmc_run(steps: int):
         b.copy_(a)
     torch.cuda.synchronize()
     log(f"[pmc] 5 copies of {4 * n} bytes done")
-    for w in PMC_GRIDS:
+    w = PMC_SMALL
+    p = solver.make_params(w.nx, w.ny, w.r, w.gamma, re=w.re, u_lid=w.u_lid,
+                           storage=STORAGE[w.storage])
+    sol = solver.Solver(p, device="cuda:0")
+    capi.prc_set_tile(p, RESIDENT_TILE)
+    for _ in range(PMC_SHORT_LAUNCHES):
+        sol.step(PMC_SHORT_STEPS)
+    torch.cuda.synchronize()
+    capi.prc_set_tile(p, -1)
+    del sol
+    capi.prc_tune(p)
+    torch.cuda.synchronize()
+    log(f"[pmc] {w.name}: {PMC_SHORT_LAUNCHES} resident launches of {PMC_SHORT_STEPS} steps "
+        "and the tuner done")
+    for w in PMC_BIG:
         p = solver.make_params(w.nx, w.ny, w.r, w.gamma, re=w.re, u_lid=w.u_lid,
                                storage=STORAGE[w.storage])
-        from paper_2208_03562_amd import capi
-        capi.prc_tune(p)  # same tile shape as the timed benchmark
-        sol = solver.Solver(p, device="cuda:0")
-        n = steps if w is PMC_GRIDS[0] else min(steps, 64)
-        sol.step(n)
+        capi.prc_tune(p)
         torch.cuda.synchronize()
-        log(f"[pmc] {n} steps of {w.name} done")
-        del sol
+        log(f"[pmc] {w.name}: tuner done")
 
 
 def oracle_parity(w: workloads.Cavity, wc: workloads.Cavity):
@@ -304,80 +374,101 @@ def oracle_parity(w: workloads.Cavity, wc: workloads.Cavity):
     return out
 
 
-PMC_COPY_BYTES = 256 * 2 ** 20  # bytes read and bytes written by pmc_run's copy
-PMC_GRIDS = (workloads.CAVITY_1024x512_F32, workloads.CAVITY_4096x2048_F32)
+CTYPE_STORAGE = (("double", "f64"), ("float", "f32"), ("__hip_bfloat16", "bf16"),
+                 ("__half", "f16"))
+SQ_COUNTERS = {"SQ_INSTS_VALU": "valu_insts", "SQ_INSTS_LDS": "lds_insts",
+               "SQ_INSTS_SALU": "salu_insts", "SQ_LDS_BANK_CONFLICT": "lds_bank_conflict_cycles"}
 
 
 def traffic_from_counters(pmc_dir: str):
-    """Write profiles/traffic.json from two rocprofv3 --pmc runs of
-    `bench.py --pmc-run N` (pmc_dir/FETCH_SIZE and pmc_dir/WRITE_SIZE, CSV
-    output named run_*).  Each counter is scaled by what it reads for the
-    256 MiB copy and averaged over the dispatches of each sweep instance on
-    each grid (the tuner dispatches every tile shape, so every instance the
-    benchmark may pick is covered); bytes per launch, per grid and instance."""
+    """Write profiles/traffic.json from the counter runs of `bench.py
+    --pmc-run` in pmc_dir (subfolders FETCH_SIZE, WRITE_SIZE and SQ, CSV output
+    named run_*): per grid and sweep instance the mean per dispatch of HBM
+    bytes read and written (FETCH_SIZE, WRITE_SIZE in KiB, each scaled by its
+    reading for the 256 MiB copy) and of the SQ instruction counters.  The
+    resident sweep's dispatches are told apart by order: the first
+    PMC_SHORT_LAUNCHES are PMC_SHORT_STEPS-step launches (key `name@20`), the
+    others the tuner's 1000-step launches (`name@1000`)."""
     import collections
     import csv
 
     from paper_2208_03562_amd import build
 
-    rec = {"source_hash": build.source_hash(), "copy_scale": {}, "bytes_per_launch": {},
-           "note": "HBM bytes per launch of each sweep instance: FETCH_SIZE and WRITE_SIZE "
-                   "(KiB per dispatch) each scaled by its reading for a 256 MiB device copy"}
-    def per_kernel(rows, ctr):
-        """{grid name: {kernel: mean counter value per dispatch}} of the sweeps"""
-        out = {}
-        for w in PMC_GRIDS:
-            groups = collections.defaultdict(list)
-            # sweeps launch a thread per node; the resident sweep 1024 threads
-            # per 64 x 32 subdomain, in whole groups of eight
-            subs = -(-w.nx // 64) * -(-w.ny // 32)
-            resident_threads = -(-subs // 8) * 8 * 1024
-            for r in rows:
-                name, grid = r["Kernel_Name"], int(r["Grid_Size"])
-                if r["Counter_Name"] == ctr and (
-                        ("k_sweep" in name and grid == w.nx * w.ny)
-                        or ("k_resident" in name and grid == resident_threads)):
-                    groups[name.split("(")[0].replace("void ", "")].append(
-                        float(r["Counter_Value"]))
-            out[w.name] = {k: sum(v) / len(v) for k, v in groups.items()}
-        return out
+    grids = {w.nx * w.ny: (w.nx, w.ny) for w in (PMC_SMALL,) + PMC_BIG}
 
-    per = collections.defaultdict(lambda: collections.defaultdict(float))
-    for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
-        rows = list(csv.DictReader(open(os.path.join(pmc_dir, ctr, "run_counter_collection.csv"))))
-        copy = [(int(r["Grid_Size"]), float(r["Counter_Value"])) for r in rows
-                if "copyBuffer" in r["Kernel_Name"] and r["Counter_Name"] == ctr]
-        big = max(g for g, _ in copy)
-        copy = [v for g, v in copy if g == big]
-        scale = PMC_COPY_BYTES / (sum(copy) / len(copy) * 1024.0)
+    def label(name, grid_threads):
+        """(grid key, instance key) of a sweep dispatch, else None"""
+        base = name.split("(")[0].replace("void ", "")
+        st = next((s for c, s in CTYPE_STORAGE if f"<{c}," in base), None)
+        if st is None:
+            return None
+        if "k_resident" in base:
+            return grid_key(PMC_SMALL.nx, PMC_SMALL.ny, st), base
+        if "k_sweep" in base and grid_threads in grids:
+            return grid_key(*grids[grid_threads], st), base
+        return None
+
+    def per_dispatch(ctr_dir):
+        """{counter: {(grid, instance): [values in dispatch order]}}"""
+        rows = list(csv.DictReader(open(os.path.join(pmc_dir, ctr_dir,
+                                                     "run_counter_collection.csv"))))
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+        out = collections.defaultdict(lambda: collections.defaultdict(list))
+        copy = collections.defaultdict(list)
+        seen_res = collections.Counter()
+        for r in rows:
+            ctr, name, g = r["Counter_Name"], r["Kernel_Name"], int(r["Grid_Size"])
+            v = float(r["Counter_Value"])
+            if "copyBuffer" in name:
+                copy[(ctr, g)].append(v)
+                continue
+            lab = label(name, g)
+            if lab is None:
+                continue
+            gk, inst = lab
+            if "k_resident" in inst:
+                k = seen_res[(ctr, inst)]
+                seen_res[(ctr, inst)] += 1
+                inst += f"@{PMC_SHORT_STEPS}" if k < PMC_SHORT_LAUNCHES else "@1000"
+            out[ctr][(gk, inst)].append(v)
+        return out, copy
+
+    rec = {"source_hash": build.source_hash(), "copy_scale": {}, "per_launch": {},
+           "note": "per sweep dispatch: HBM bytes from FETCH_SIZE and WRITE_SIZE (KiB) each "
+                   "scaled by its reading for a 256 MiB device copy; SQ instruction counts are "
+                   "wave instructions over all CUs; resident-sweep keys carry the steps per "
+                   "launch"}
+    per = collections.defaultdict(dict)
+    for ctr, field in (("FETCH_SIZE", "fetch_bytes"), ("WRITE_SIZE", "write_bytes")):
+        vals, copy = per_dispatch(ctr)
+        big = max(g for (c, g) in copy if c == ctr)
+        ref = copy[(ctr, big)]
+        scale = PMC_COPY_BYTES / (sum(ref) / len(ref) * 1024.0)
         rec["copy_scale"][ctr] = round(scale, 5)
-        for wname, kernels in per_kernel(rows, ctr).items():
-            for name, v in kernels.items():
-                per[wname][name] += v * 1024.0 * scale
-    for wname, kernels in per.items():
-        rec["bytes_per_launch"][wname] = {k: int(round(v)) for k, v in sorted(kernels.items())}
-    # instructions issued per launch (wave instructions, all CUs), if a third
-    # run counted them
-    sq = os.path.join(pmc_dir, "SQ", "run_counter_collection.csv")
-    if os.path.exists(sq):
-        rows = list(csv.DictReader(open(sq)))
-        for ctr, key in (("SQ_INSTS_VALU", "valu_insts_per_launch"),
-                         ("SQ_INSTS_LDS", "lds_insts_per_launch")):
-            rec[key] = {wname: {k: int(round(v)) for k, v in sorted(kernels.items())}
-                        for wname, kernels in per_kernel(rows, ctr).items()}
+        for (gk, inst), v in vals[ctr].items():
+            per[(gk, inst)][field] = int(round(sum(v) / len(v) * 1024.0 * scale))
+            per[(gk, inst)]["dispatches"] = len(v)
+    if os.path.isdir(os.path.join(pmc_dir, "SQ")):
+        vals, _ = per_dispatch("SQ")
+        for ctr, field in SQ_COUNTERS.items():
+            for (gk, inst), v in vals.get(ctr, {}).items():
+                per[(gk, inst)][field] = int(round(sum(v) / len(v)))
+    for (gk, inst), d in sorted(per.items()):
+        if "fetch_bytes" in d and "write_bytes" in d:
+            d["hbm_bytes"] = d["fetch_bytes"] + d["write_bytes"]
+        rec["per_launch"].setdefault(gk, {})[inst] = d
     path = os.path.join(ROOT, "profiles", "traffic.json")
     with open(path, "w") as fh:
         json.dump(rec, fh, indent=1)
     print(json.dumps(rec))
 
 
-def steps_per_launch(tile: int) -> int:
-    """Time steps per sweep launch in the timed loop: the tile's own count, or
-    for the resident sweep (0: any count) one launch per call of CHECK_EVERY
-    steps."""
+def steps_per_launch(tile: int, chunk: int) -> int:
+    """Time steps per sweep launch in the timed loop: the tile's own count,
+    or for the resident sweep (0: any count) one launch per chunk."""
     from paper_2208_03562_amd import capi
     steps = capi.prc_tile_info(tile)[2]
-    return steps if steps > 0 else CHECK_EVERY
+    return steps if steps > 0 else chunk
 
 
 def sweep_kernel_name(storage: str, bc: int, tile: int, state_bytes: int) -> str:
@@ -400,7 +491,9 @@ def sweep_kernel_name(storage: str, bc: int, tile: int, state_bytes: int) -> str
 def trace_summary(trace_dir: str):
     """Markdown table of a rocprofv3 --kernel-trace run of bench.py (CSV output
     named bench_*): dispatches, mean, median and minimum duration per kernel
-    instance and grid size (the library's --stats table merges grids)."""
+    instance and grid size; the resident sweep's launches are further split
+    into groups of similar length (launches of different step counts share
+    one instance and grid)."""
     import collections
     import csv
     import statistics
@@ -411,18 +504,33 @@ def trace_summary(trace_dir: str):
         name = r["Kernel_Name"].split("(")[0].replace("void ", "")
         groups[(name, int(r["Grid_Size_X"]))].append(
             int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    out = []
+    for (name, grid), v in groups.items():
+        v = sorted(v)
+        if "k_resident" in name:
+            # split where a duration exceeds the previous one by half
+            parts, cur = [], [v[0]]
+            for x in v[1:]:
+                if x > 1.5 * cur[-1]:
+                    parts.append(cur)
+                    cur = []
+                cur.append(x)
+            parts.append(cur)
+        else:
+            parts = [v]
+        for part in parts:
+            out.append((name, grid, part))
     print("| kernel | grid (threads) | dispatches | mean us | median us | min us |")
     print("|---|---|---|---|---|---|")
-    for (name, grid), v in sorted(groups.items(), key=lambda kv: -sum(kv[1])):
-        v = sorted(v)
+    for name, grid, v in sorted(out, key=lambda t: -sum(t[2])):
         print(f"| `{name}` | {grid} | {len(v)} | {statistics.mean(v) / 1e3:.3f} | "
               f"{v[len(v) // 2] / 1e3:.3f} | {v[0] / 1e3:.3f} |")
 
 
-def measured_traffic(w: workloads.Cavity, kernel: str, key: str = "bytes_per_launch"):
-    """HBM bytes per launch of sweep instance `kernel` on grid w (or another
-    per-launch count, `key`) from the committed counter summary, if it was
-    taken on the current library code (else None)."""
+def measured_counters(w: workloads.Cavity, kernel: str, per_launch: int):
+    """Per-launch counters of sweep instance `kernel` on grid w from the
+    committed summary (resident sweep: at `per_launch` steps per launch), if
+    they were taken on the current library code, else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         rec = json.load(open(path))
@@ -431,7 +539,54 @@ def measured_traffic(w: workloads.Cavity, kernel: str, key: str = "bytes_per_lau
     from paper_2208_03562_amd import build
     if rec.get("source_hash") != build.source_hash():
         return None
-    return rec.get(key, {}).get(w.name, {}).get(kernel)
+    key = f"{kernel}@{per_launch}" if "k_resident" in kernel else kernel
+    return rec.get("per_launch", {}).get(grid_key(w.nx, w.ny, w.storage), {}).get(key)
+
+
+def roofline_of(w: workloads.Cavity, res: dict, storage: str):
+    """Roofline record of the sweep instance a timed run used: its launch
+    duration (HIP events: the resident sweep's chunk is one launch; other
+    shapes average the chunk over its launches), algorithmic and measured HBM
+    bytes per launch, and VALU issue.  `bound` is the resource with the
+    larger measured fraction: HBM bytes actually moved, or VALU wave
+    instructions issued; the algorithmic byte rate is reported beside it."""
+    from paper_2208_03562_amd import capi, solver
+    tile = res["tile"]
+    per_launch = steps_per_launch(tile, res["chunk_steps"])
+    p = solver.make_params(w.nx, w.ny, w.r, w.gamma, re=w.re, u_lid=w.u_lid,
+                           storage=STORAGE[storage])
+    kernel = sweep_kernel_name(storage, 0, tile, capi.prc_state_bytes(p))
+    resident = capi.prc_tile_info(tile)[2] == 0
+    kernel_us = res["chunk_us"] if resident else res["sweep_us"] * per_launch
+    nodes = w.nx * w.ny
+    alg = BYTES_PER_NODE[storage] * nodes * per_launch
+    c = measured_counters(w, kernel, per_launch)
+    rec = {"kernel": kernel, "steps_per_launch": per_launch, "kernel_us": round(kernel_us, 3),
+           "algorithmic_bytes": alg,
+           "algorithmic_gbs": round(alg / (kernel_us * 1e-6) / 1e9, 1),
+           "algorithmic_frac": round(alg / (kernel_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+           "traffic": c.get("hbm_bytes") if c else None, "traffic_unit": "bytes per launch"}
+    fr = {}
+    if c and "hbm_bytes" in c:
+        gbs = c["hbm_bytes"] / (kernel_us * 1e-6) / 1e9
+        fr["hbm"] = (gbs, HBM_PEAK_GBS, "GB/s")
+    if c and "valu_insts" in c:
+        gi = c["valu_insts"] / (kernel_us * 1e-6) / 1e9
+        fr["alu"] = (gi, VALU_PEAK_GINST_S, "G VALU wave64 instructions/s")
+        rec["valu_insts_per_node_update"] = round(c["valu_insts"] * 64 / (nodes * per_launch), 1)
+    if c and "lds_insts" in c:
+        rec["lds_insts_per_node_update"] = round(c["lds_insts"] * 64 / (nodes * per_launch), 1)
+    if fr:
+        bound = max(fr, key=lambda k: fr[k][0] / fr[k][1])
+        a, pk, unit = fr[bound]
+        rec.update(bound=bound, achieved=round(a, 1), peak=pk, unit=unit,
+                   frac=round(a / pk, 4))
+        rec["fractions"] = {k: round(v[0] / v[1], 4) for k, v in fr.items()}
+    else:  # no counters for this code: the algorithmic byte rate only
+        rec.update(bound="hbm", achieved=rec["algorithmic_gbs"], peak=HBM_PEAK_GBS,
+                   unit="GB/s (algorithmic bytes; no counters for this code)",
+                   frac=rec["algorithmic_frac"])
+    return rec
 
 
 def main():
@@ -475,8 +630,13 @@ def main():
 
     w = workloads.CAVITY_1024x512_F32
     main_res = run_gpu(w, args.steps, args.warmup)
+    main_roof = roofline_of(w, main_res, w.storage)
     wc = workloads.CAVITY_1024x512_F32_MA006
     comp = run_gpu(wc, args.steps, args.warmup)
+    # steady state: the survey's recipe for this cavity (1000-step warm-up
+    # and more, at least 10,000 timed steps, checks every 1000 inside)
+    steady = run_gpu(w, STEADY_STEPS, STEADY_WARMUP)
+    steady_roof = roofline_of(w, steady, w.storage)
     big = {}
     if args.hbm_steps > 0:
         for wh in (workloads.CAVITY_4096x2048_F32, workloads.CAVITY_4096x2048_MA002["f32"],
@@ -486,37 +646,15 @@ def main():
             r = run_gpu(wh, args.hbm_steps, min(args.warmup, 500))
             big[wh.name] = dict(
                 workload=wh.name, u_lid=round(wh.u_lid, 6), mlups=round(r["mlups"], 1),
-                sweep_us=round(r["sweep_us"], 2), achieved_gbs=round(r["sweep_gbs"], 1),
-                tile=r["tile"], steps_per_launch=steps_per_launch(r["tile"]),
-                frac=round(r["sweep_gbs"] / HBM_PEAK_GBS, 4),
-                bytes_per_node=BYTES_PER_NODE[wh.storage], diverged_at_step=r["diverged_at"])
+                sweep_us=round(r["sweep_us"], 2), tile=r["tile"],
+                bytes_per_node=BYTES_PER_NODE[wh.storage], diverged_at_step=r["diverged_at"],
+                roofline=roofline_of(wh, r, wh.storage))
     batch = run_batch(args.batch_instances, 16) if args.batch_instances > 0 else None
     serve = (run_serve(args.serve_requests, min(args.serve_requests, 50),
                        batch["mlups"] if batch else main_res["mlups"])
              if args.serve_requests > 0 else None)
     parity = oracle_parity(w, wc) if args.cpu_budget > 0 else None
     cpu = run_cpu_baseline(w, args.cpu_budget) if args.cpu_budget > 0 else None
-    per_launch = steps_per_launch(main_res["tile"])
-    from paper_2208_03562_amd import solver as _solver
-    state_bytes = capi.prc_state_bytes(_solver.make_params(
-        w.nx, w.ny, w.r, w.gamma, re=w.re, u_lid=w.u_lid, storage=STORAGE[w.storage]))
-    kernel = sweep_kernel_name(w.storage, 0, main_res["tile"], state_bytes)
-    traffic = measured_traffic(w, kernel)
-    valu_insts = measured_traffic(w, kernel, "valu_insts_per_launch")
-    nodes = w.nx * w.ny
-    kernel_us = main_res["sweep_us"] * per_launch
-    valu = None
-    if valu_insts:
-        # VALU issue: a wave64 instruction takes 4 cycles of a 16-lane SIMD;
-        # 256 CUs x 4 SIMDs at 2.4 GHz issue 614.4 G of them per second
-        # (FP32 without packed instructions)
-        achieved = valu_insts / (kernel_us * 1e-6) / 1e9
-        valu = {"insts_per_launch": valu_insts,
-                "insts_per_node_update": round(valu_insts * 64 / (nodes * per_launch), 1),
-                "achieved_ginst_s": round(achieved, 1), "peak_ginst_s": VALU_PEAK_GINST_S,
-                "frac": round(achieved / VALU_PEAK_GINST_S, 4),
-                "note": "wave instructions (SQ_INSTS_VALU, committed counter run) / this run's "
-                        "launch time; peak: 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles"}
 
     out = {
         "metric": "MLUPS",
@@ -534,31 +672,21 @@ def main():
         "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "r": w.r, "re": w.re,
                    "u_lid": w.u_lid, "gamma": w.gamma, "storage": "f32 deviations",
                    "residual_every": CHECK_EVERY, "bytes_per_node": BYTES_PER_NODE[w.storage]},
-        "roofline": {"bound": "hbm", "achieved": round(main_res["sweep_gbs"], 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(main_res["sweep_gbs"] / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "traffic_unit": "bytes per launch",
-                     "algorithmic_bytes": BYTES_PER_NODE[w.storage] * nodes * per_launch,
-                     "kernel": kernel,
-                     "steps_per_launch": per_launch,
-                     "kernel_us": round(kernel_us, 3),
-                     "valu": valu,
-                     "note": f"72 B per node update (9 FP32 reads + 9 FP32 writes) x {nodes} "
-                             f"nodes x {per_launch} step(s) per launch; achieved = those bytes / "
-                             "launch time.  The resident sweep keeps the state in LDS for all "
-                             "the steps of a launch and moves only the subdomains' edges "
-                             "between steps (traffic); a two-step launch keeps the intermediate "
-                             "state in LDS.  Either moves fewer bytes than the algorithmic "
-                             "count"},
+        "roofline": dict(main_roof, note=ROOFLINE_NOTE),
+        "resident_ok": main_res["resident_ok"],
         "solution": {"diverged_at_step": main_res["diverged_at"],
                      "residual_last": main_res["residual_last"],
                      "note": "U = 0.05 with gamma = 0.1 is outside the scheme's stable range; "
                              "the FP64 oracle diverges too (about step 100). The sweep is "
                              "branch-free, so its speed does not depend on the values."},
+        "steady_state": {"workload": w.name, "steps": STEADY_STEPS, "warmup": STEADY_WARMUP,
+                         "mlups": round(steady["mlups"], 1),
+                         "ms_per_step": round(steady["ms_per_step"], 5),
+                         "sweep_us": round(steady["sweep_us"], 3),
+                         "resident_ok": steady["resident_ok"], "roofline": steady_roof},
         "stable_companion": {"workload": wc.name, "u_lid": round(wc.u_lid, 6),
                              "mlups": round(comp["mlups"], 1),
                              "sweep_us": round(comp["sweep_us"], 3),
-                             "achieved_gbs": round(comp["sweep_gbs"], 1),
                              "residual_last": comp["residual_last"],
                              "diverged_at_step": comp["diverged_at"]},
         "hbm_grids": big or None,
@@ -568,6 +696,20 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+STEADY_STEPS, STEADY_WARMUP = 12000, 2000
+ROOFLINE_NOTE = ("kernel_us: HIP events on the solver's stream around the timed launch (the "
+                 "resident sweep runs a chunk of steps as one launch; other shapes: the mean "
+                 "over the chunk's launches).  traffic: HBM bytes per launch from the committed "
+                 "FETCH_SIZE + WRITE_SIZE counters of this instance at this launch length, each "
+                 "scaled by its reading for a 256 MiB copy; null if the code changed since.  "
+                 "bound/frac: the measured resource with the larger fraction -- HBM bytes "
+                 "actually moved against 8 TB/s, or VALU wave64 instructions (committed "
+                 "SQ_INSTS_VALU) against 614.4 G/s (256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles).  "
+                 "algorithmic_*: 72 B per node update (9 FP32 reads + 9 writes) x nodes x "
+                 "steps per launch over the launch time; the resident sweep keeps the state in "
+                 "LDS between steps and moves fewer bytes than that")
 
 
 if __name__ == "__main__":
