@@ -121,7 +121,10 @@ def run_gpu(w: workloads.Cavity, steps: int, warmup: int):
 
 
 BATCH_TOL, BATCH_CHECK, BATCH_MAX_STEPS = 1e-7, 500, 100000
-SERVE_TOL, SERVE_CHECK, SERVE_MAX_STEPS = 1e-7, 500, 20000
+# serving: each request to R < 1e-7 (checks every 500 steps) or 200,000 steps;
+# about a third of the trace's requests converge within that budget (the
+# rest are large cavities at high Re that need more, or diverge)
+SERVE_TOL, SERVE_CHECK, SERVE_MAX_STEPS = 1e-7, 500, 200000
 
 
 def run_batch(n_inst: int, solo_sample: int):
@@ -194,10 +197,12 @@ def run_batch(n_inst: int, solo_sample: int):
 
 def run_serve(n_req: int, solo_req: int, mlups_hint: float):
     """Serving: the seeded Poisson trace (seed 1, unit rate, scaled) of
-    steady-state solve requests, each to R < 1e-7 or 20000 steps.  The rate
-    is 80 % of the capacity implied by mlups_hint for requests that use their
-    whole step budget.  Then the first solo_req requests of the same trace
-    served one at a time."""
+    steady-state solve requests, each to R < 1e-7 or SERVE_MAX_STEPS steps,
+    fed from this process to an online server (prc_server_*) at their
+    arrival times.  The rate is 80 % of the capacity implied by mlups_hint
+    for requests that use their whole step budget (converged requests use
+    less, so the load is lower).  Then the first solo_req requests of the
+    same trace served one at a time (max_active = 1)."""
     import numpy as np
     from paper_2208_03562_amd import serving, solver
 
@@ -210,10 +215,10 @@ def run_serve(n_req: int, solo_req: int, mlups_hint: float):
     budget = 32 << 30
     kw = dict(tol=SERVE_TOL, check_every=SERVE_CHECK, max_steps=SERVE_MAX_STEPS,
               hbm_budget=budget)
-    on = serving.serve(ps, arrivals, **kw)
+    on = serving.serve_online(ps, arrivals, **kw)
     s_on = serving.summary(on)
     log(f"[bench] serving {n_req} requests at {lam:.2f}/s: {s_on}")
-    one = serving.serve(ps[:solo_req], arrivals[:solo_req], max_active=1, **kw)
+    one = serving.serve_online(ps[:solo_req], arrivals[:solo_req], max_active=1, **kw)
     s_one = serving.summary(one)
     s_on_head = serving.summary(on[:solo_req])
     log(f"[bench] first {solo_req} one at a time: {s_one}")
@@ -224,6 +229,7 @@ def run_serve(n_req: int, solo_req: int, mlups_hint: float):
                     "128..2048, Ny 128..1024, r, gamma, Re as the batch workload; FP32",
         "tol": SERVE_TOL, "check_every": SERVE_CHECK, "max_steps": SERVE_MAX_STEPS,
         "rate_per_s": round(lam, 4), "hbm_budget_bytes": budget,
+        "interface": "online server: each request submitted at its arrival time, results polled",
         "batched": rnd(s_on),
         "batched_first": rnd(s_on_head),
         "one_at_a_time_first": rnd(s_one),
@@ -599,7 +605,7 @@ def main():
                     help="print per-grid kernel durations of a kernel-trace run in this folder")
     ap.add_argument("--batch-instances", type=int, default=256,
                     help="instances of the batched-solve workload (0: skip)")
-    ap.add_argument("--serve-requests", type=int, default=500,
+    ap.add_argument("--serve-requests", type=int, default=100,
                     help="requests of the serving trace (0: skip)")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20000)
@@ -650,7 +656,7 @@ def main():
                 bytes_per_node=BYTES_PER_NODE[wh.storage], diverged_at_step=r["diverged_at"],
                 roofline=roofline_of(wh, r, wh.storage))
     batch = run_batch(args.batch_instances, 16) if args.batch_instances > 0 else None
-    serve = (run_serve(args.serve_requests, min(args.serve_requests, 50),
+    serve = (run_serve(args.serve_requests, min(args.serve_requests, 20),
                        batch["mlups"] if batch else main_res["mlups"])
              if args.serve_requests > 0 else None)
     parity = oracle_parity(w, wc) if args.cpu_budget > 0 else None

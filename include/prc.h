@@ -425,11 +425,73 @@ typedef struct {
 } prc_serve_config;
 
 /* Serve requests reqs[0 .. n) (host array, arrivals non-decreasing) and write
- * res[0 .. n) (host).  Allocates one pool of cfg->hbm_budget bytes
- * (hipMalloc) for the requests' buffers and frees it before returning.
+ * res[0 .. n) (host): a server (prc_server_create, below) to which the
+ * calling thread submits each request at its arrival time (seconds after the
+ * call) while collecting results.  Allocates one pool of cfg->hbm_budget
+ * bytes (hipMalloc) for the requests' buffers and frees it before returning.
  * Blocks until every request has its result; synchronises the stream. */
 prc_status prc_serve(const prc_serve_config *cfg, const prc_request *reqs, int32_t n,
                      prc_result *res, hipStream_t stream);
+
+/* ---- Online serving: requests submitted while the server runs ----------
+ *
+ * prc_server_create starts a server on the current device: a pool of
+ * cfg->hbm_budget device bytes (one hipMalloc), a batch, and a host worker
+ * thread that runs the loop described above on `stream` -- admit submitted
+ * requests whose buffers fit, advance the batch one interval, hand finished
+ * results to the host, return their memory -- until prc_server_destroy; it
+ * sleeps while nothing is submitted.  Requests are submitted at any time,
+ * from any thread, and the call returns at once; finished ones are collected
+ * with prc_server_poll.  Admission follows submission order, except that a
+ * request that does not fit yet is passed by later ones that do, for at most
+ * 8 intervals; after that nothing is admitted before it.  Each result is bit
+ * for bit that of prc_solve on the same problem with the server's tol,
+ * check_every and max_steps.  prc_serve above replays a trace of arrivals
+ * through such a server.
+ */
+typedef struct prc_server prc_server;
+
+typedef struct {
+    int64_t ticket;    /* as returned by prc_server_submit */
+    int32_t status;    /* prc_member_status, or PRC_EINVAL if rejected (invalid
+                          problem, other storage or bc, larger than the pool) */
+    int32_t reserved;
+    int64_t steps;     /* time steps taken */
+    double residual;   /* relative residual of its last check */
+    double submit_s;   /* seconds since prc_server_create: submitted, */
+    double admit_s;    /* its state set up on the GPU, */
+    double done_s;     /* its result on the host */
+} prc_server_result;
+
+/* Start a server (see above); cfg as for prc_serve.  *out receives it.
+ * Allocates the pool (PRC_EHIP if that fails) and starts the worker. */
+prc_status prc_server_create(const prc_serve_config *cfg, hipStream_t stream,
+                             prc_server **out);
+
+/* Queue a steady-state solve of problem *p (copied).  ux, uy: host
+ * double[ny][nx] each for the final velocity, or NULL; they must stay valid
+ * until this request's result has been polled.  *ticket (may be NULL)
+ * receives its id (0, 1, 2, ... per server).  Thread safe; returns at once.
+ * Fails if the server has stopped or its worker failed. */
+prc_status prc_server_submit(prc_server *srv, const prc_params *p, double *ux,
+                             double *uy, int64_t *ticket);
+
+/* Take up to cap finished results (host array out), oldest first; *n
+ * receives how many.  Waits up to wait_s seconds for a first one if none is
+ * ready (0: does not wait).  Thread safe.  Returns the worker's error once
+ * it has failed and no result is left. */
+prc_status prc_server_poll(prc_server *srv, double wait_s, prc_server_result *out,
+                           int32_t cap, int32_t *n);
+
+/* Requests waiting for admission, in the batch, and finished but not yet
+ * polled (any pointer may be NULL). */
+prc_status prc_server_status(prc_server *srv, int32_t *waiting, int32_t *active,
+                             int32_t *unpolled);
+
+/* Stop the worker after its current interval, synchronise the stream, free
+ * the pool and the server.  Requests not finished by then are dropped (no
+ * result).  NULL is allowed. */
+prc_status prc_server_destroy(prc_server *srv);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *prc_last_error(void);

@@ -64,6 +64,13 @@ class prc_result(ctypes.Structure):
                 ("admit_s", ctypes.c_double), ("done_s", ctypes.c_double)]
 
 
+class prc_server_result(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_int64), ("status", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("steps", ctypes.c_int64),
+                ("residual", ctypes.c_double), ("submit_s", ctypes.c_double),
+                ("admit_s", ctypes.c_double), ("done_s", ctypes.c_double)]
+
+
 class prc_serve_config(ctypes.Structure):
     _fields_ = [("storage", ctypes.c_int32), ("bc", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("check_every", ctypes.c_int64), ("max_steps", ctypes.c_int64),
@@ -122,6 +129,15 @@ _PROTOS = {
                                        _VP]),
     "prc_batch_tune": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int32), _VP]),
     "prc_batch_set_tile": (ctypes.c_int, [_VP, ctypes.c_int32]),
+    "prc_server_create": (ctypes.c_int, [ctypes.POINTER(prc_serve_config), _VP,
+                                        ctypes.POINTER(_VP)]),
+    "prc_server_submit": (ctypes.c_int, [_VP, _P, _VP, _VP, _I64P]),
+    "prc_server_poll": (ctypes.c_int, [_VP, ctypes.c_double, ctypes.POINTER(prc_server_result),
+                                      ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "prc_server_status": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_int32)]),
+    "prc_server_destroy": (ctypes.c_int, [_VP]),
     "prc_serve": (ctypes.c_int, [ctypes.POINTER(prc_serve_config), ctypes.POINTER(prc_request),
                                  ctypes.c_int32, ctypes.POINTER(prc_result), _VP]),
 }
@@ -360,3 +376,35 @@ def prc_serve(cfg: prc_serve_config, reqs, stream: int = 0):
     res = (prc_result * max(1, n))()
     _check("prc_serve", lib().prc_serve(ctypes.byref(cfg), arr, n, res, stream))
     return [res[i] for i in range(n)]
+
+
+def prc_server_create(cfg: prc_serve_config, stream: int = 0) -> int:
+    h = _VP()
+    _check("prc_server_create", lib().prc_server_create(ctypes.byref(cfg), stream, ctypes.byref(h)))
+    return h.value
+
+
+def prc_server_submit(srv: int, p: prc_params, ux: int | None = None, uy: int | None = None) -> int:
+    t = ctypes.c_int64()
+    _check("prc_server_submit", lib().prc_server_submit(srv, ctypes.byref(p), ux, uy,
+                                                        ctypes.byref(t)))
+    return t.value
+
+
+def prc_server_poll(srv: int, wait_s: float = 0.0, cap: int = 256):
+    out = (prc_server_result * max(1, cap))()
+    n = ctypes.c_int32()
+    _check("prc_server_poll", lib().prc_server_poll(srv, float(wait_s), out, int(cap),
+                                                    ctypes.byref(n)))
+    return [out[i] for i in range(n.value)]
+
+
+def prc_server_status(srv: int):
+    w, a, u = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check("prc_server_status", lib().prc_server_status(srv, ctypes.byref(w), ctypes.byref(a),
+                                                        ctypes.byref(u)))
+    return w.value, a.value, u.value
+
+
+def prc_server_destroy(srv: int) -> None:
+    _check("prc_server_destroy", lib().prc_server_destroy(srv))

@@ -82,3 +82,76 @@ def test_rejected_requests(alone):
                            max_steps=MAX, hbm_budget=budget, fields=True)
     assert served[1].status == capi.PRC_EINVAL and served[3].status == capi.PRC_EINVAL
     check_same([served[0], served[2]], [alone[0], alone[2]])
+
+
+def test_online_server_results_are_the_solo_solves(alone):
+    """Requests submitted while others are already running (arrivals not
+    known in advance), polled as they finish: each result is the solo solve."""
+    import time
+    from paper_2208_03562_amd import serving
+    srv = serving.OnlineServer(tol=TOL, check_every=K, max_steps=MAX, hbm_budget=64 << 20)
+    try:
+        tickets = {srv.submit(lib_params(s), fields=True): i for i, s in enumerate(PROBLEMS[:3])}
+        got = {}
+        t0 = time.perf_counter()
+        while srv.status()[1] == 0 and time.perf_counter() - t0 < 30:  # wait until running
+            for f in srv.poll(0.01):
+                got[tickets[f.ticket]] = f
+        for i, s in enumerate(PROBLEMS[3:], start=3):
+            tickets[srv.submit(lib_params(s), fields=True)] = i
+            for f in srv.poll(0.005):
+                got[tickets[f.ticket]] = f
+        while len(got) < len(PROBLEMS) and time.perf_counter() - t0 < 120:
+            for f in srv.poll(1.0):
+                got[tickets[f.ticket]] = f
+        assert len(got) == len(PROBLEMS)
+        served = [serving.Served(got[i].status, got[i].steps, got[i].residual, got[i].submit_s,
+                                 got[i].admit_s, got[i].done_s, got[i].ux, got[i].uy)
+                  for i in range(len(PROBLEMS))]
+        check_same(served, alone)
+        assert srv.status() == (0, 0, 0)
+    finally:
+        srv.close()
+
+
+def test_online_server_rejects_other_storage_and_stops_mid_run():
+    from paper_2208_03562_amd import capi, serving
+    srv = serving.OnlineServer(tol=1e-12, check_every=100, max_steps=100000,
+                               hbm_budget=64 << 20)
+    try:
+        bad = lib_params(spec(32, 32, 1.0, 1.0, omega_nu=1.2, u_lid=0.02, storage="f64"))
+        t_bad = srv.submit(bad)
+        t_long = srv.submit(lib_params(spec(200, 100, 2.0, 1.0, omega_nu=1.5, u_lid=0.02)))
+        got = {}
+        for _ in range(100):
+            for f in srv.poll(0.1):
+                got[f.ticket] = f
+            if t_bad in got:
+                break
+        assert got[t_bad].status == capi.PRC_EINVAL
+        assert t_long not in got
+    finally:
+        srv.close()  # stops after the current interval; the long request is dropped
+
+
+def test_served_fp64_requests_match_the_oracle(O):
+    """An FP64 server, two small cavities submitted together: steps, status
+    and final velocity against the oracle's solve with the same tol and check
+    interval (round-off only)."""
+    import numpy as np
+    from paper_2208_03562_amd import capi, serving
+    from tests.common import oracle_params
+    specs = [spec(24, 12, 2.0, 0.5, re=50.0, omega_nu=None, u_lid=0.05, storage="f64"),
+             spec(20, 16, 1.0, 1.0, re=40.0, omega_nu=None, u_lid=0.03, storage="f64")]
+    tol, k, mx = 1e-9, 200, 60000
+    served = serving.serve_online([lib_params(s) for s in specs], [0.0, 0.0],
+                                  storage=capi.PRC_F64, tol=tol, check_every=k, max_steps=mx,
+                                  hbm_budget=16 << 20, fields=True)
+    for s, r in zip(specs, served):
+        po = oracle_params(O, s)
+        ft = O.rest_state(po)
+        st, n, _ = O.solve(po, ft, tol, k, mx)
+        _, oux, ouy = O.velocity(po, ft)
+        assert (r.status, r.steps) == (st, n) and st == 0, (r.status, r.steps, st, n)
+        err = max(np.abs(r.ux - oux).max(), np.abs(r.uy - ouy).max()) / s["u_lid"]
+        assert err < 1e-12, err
