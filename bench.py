@@ -237,6 +237,62 @@ def run_serve(n_req: int, solo_req: int, mlups_hint: float):
     }
 
 
+PROMO_CASE = dict(name="cavity_1024x512_r0.5_re500_g0.05_ma0.02", nx=1024, ny=512, r=0.5,
+                  gamma=0.05, re=500.0, u_lid=workloads.MA002_LID_R05)
+PROMO_TOL, PROMO_CHECK, PROMO_MAX = 1e-5, 1000, 600000
+
+
+def run_promotion():
+    """Reduced-precision storage with a path to convergence: the shallow
+    cavity of the 16-bit workload scaled down 4x per side (1024 x 512, r 0.5,
+    Re 500, gamma 0.05, Ma 0.02) solved to R < 1e-5 (checks every 1000
+    steps) in FP32 alone, and starting in FP16 / BF16 with the state promoted
+    to FP32 once the 16-bit residual stops falling; wall time, steps and the
+    final velocity against an FP64 solve to 1e-7 on the GPU (itself held to
+    the oracle by the parity tests)."""
+    import numpy as np
+    import torch
+    from paper_2208_03562_amd import capi, precision, solver
+
+    c = PROMO_CASE
+
+    def mk(st):
+        return solver.make_params(c["nx"], c["ny"], c["r"], c["gamma"], re=c["re"],
+                                  u_lid=c["u_lid"], storage=st)
+
+    ref = solver.Solver(mk(capi.PRC_F64))
+    ref.solve(PROMO_TOL / 100, PROMO_CHECK, 3 * PROMO_MAX)
+    _, ux64, uy64 = (a.cpu().numpy() for a in ref.macros())
+    del ref
+
+    def err(sol):
+        _, ux, uy = (a.cpu().numpy() for a in sol.macros())
+        return float(max(np.abs(ux - ux64).max(), np.abs(uy - uy64).max()) / c["u_lid"])
+
+    out = {"workload": c["name"], "tol": PROMO_TOL, "check_every": PROMO_CHECK}
+    sol = solver.Solver(mk(capi.PRC_F32))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, n, _ = sol.solve(PROMO_TOL, PROMO_CHECK, PROMO_MAX)
+    torch.cuda.synchronize()
+    out["f32"] = {"status": st, "steps": n, "wall_s": round(time.perf_counter() - t0, 3),
+                  "max_rel_velocity_error_vs_f64": float(f"{err(sol):.3e}")}
+    del sol
+    for name, st16 in (("f16", capi.PRC_F16), ("bf16", capi.PRC_BF16)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, n16, n, _, sol, dm = precision.promoted_solve(mk(st16), PROMO_TOL, PROMO_CHECK,
+                                                          PROMO_MAX)
+        torch.cuda.synchronize()
+        out[f"{name}_then_f32"] = {
+            "status": st, "steps_16bit": n16, "steps": n,
+            "wall_s": round(time.perf_counter() - t0, 3),
+            "max_rel_velocity_error_vs_f64": float(f"{err(sol):.3e}")}
+        del sol
+    log(f"[bench] promotion: {out}")
+    return out
+
+
 def native_oracle():
     """The oracle's C source compiled for the host that runs the benchmark
     (gcc -O3 -march=native -fopenmp: the CPU baseline's build; the source is
@@ -353,6 +409,50 @@ def pmc_run(steps: int):
         capi.prc_tune(p)
         torch.cuda.synchronize()
         log(f"[pmc] {w.name}: tuner done")
+
+
+def batch_trace_run(intervals: int):
+    """Workload of the batch kernel trace: the 256-instance batch (seed 0),
+    tuned, then `intervals` intervals of 500 steps (tol 0: nobody leaves)."""
+    import torch
+    from paper_2208_03562_amd import solver
+
+    b = solver.Batch()
+    for it in workloads.batch_instances(256, seed=0):
+        b.add(solver.make_params(it.nx, it.ny, it.r, it.gamma, re=it.re, u_lid=it.u_lid))
+    tile = b.tune()
+    torch.cuda.synchronize()
+    b.solve(0.0, BATCH_CHECK, BATCH_CHECK * intervals)
+    torch.cuda.synchronize()
+    log(f"[batch-trace] {intervals} intervals of {BATCH_CHECK} steps, tile {tile}")
+    b.close()
+
+
+def gap_summary(trace_dir: str):
+    """From a kernel trace of batch_trace_run: per interval between two
+    batched residual checks, the sweep launches, their summed duration, the
+    summed idle time between consecutive kernels and its fraction of the
+    interval."""
+    import csv
+
+    rows = list(csv.DictReader(open(os.path.join(trace_dir, "bench_kernel_trace.csv"))))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    # intervals: from the first sweep after a residual kernel to the last sweep
+    # before the next one (the timed solve only: after the tuner's trials)
+    ks = [(r["Kernel_Name"].split("(")[0].replace("void ", ""), int(r["Start_Timestamp"]),
+           int(r["End_Timestamp"])) for r in rows]
+    res_idx = [i for i, k in enumerate(ks) if "k_residual_batch" in k[0]]
+    print("| interval | sweep launches | kernel time us | idle between kernels us | span us | idle fraction |")
+    print("|---|---|---|---|---|---|")
+    for n, (a, b) in enumerate(zip(res_idx, res_idx[1:])):
+        sweeps = [k for k in ks[a + 1:b] if "k_sweep" in k[0]]
+        if len(sweeps) < 10:
+            continue
+        busy = sum(e - s for _, s, e in sweeps)
+        idle = sum(max(0, s2 - e1) for (_, _, e1), (_, s2, _) in zip(sweeps, sweeps[1:]))
+        span = sweeps[-1][2] - sweeps[0][1]
+        print(f"| {n} | {len(sweeps)} | {busy / 1e3:.1f} | {idle / 1e3:.1f} | {span / 1e3:.1f} | "
+              f"{idle / span:.4f} |")
 
 
 def oracle_parity(w: workloads.Cavity, wc: workloads.Cavity):
@@ -601,6 +701,10 @@ def main():
                     help="only run the short counter workload with this many sweeps per grid")
     ap.add_argument("--traffic-from", default="",
                     help="write profiles/traffic.json from the two counter runs in this folder")
+    ap.add_argument("--batch-trace", type=int, default=0,
+                    help="only run this many batched 500-step intervals (for a kernel trace)")
+    ap.add_argument("--gap-summary", default="",
+                    help="print per-interval launch gaps of a --batch-trace kernel trace")
     ap.add_argument("--trace-summary", default="",
                     help="print per-grid kernel durations of a kernel-trace run in this folder")
     ap.add_argument("--batch-instances", type=int, default=256,
@@ -623,6 +727,9 @@ def main():
     if args.trace_summary:
         trace_summary(args.trace_summary)
         return
+    if args.gap_summary:
+        gap_summary(args.gap_summary)
+        return
     if args.traffic_from:
         traffic_from_counters(args.traffic_from)
         return
@@ -632,6 +739,9 @@ def main():
     from paper_2208_03562_amd import capi
     if args.pmc_run > 0:
         pmc_run(args.pmc_run)
+        return
+    if args.batch_trace > 0:
+        batch_trace_run(args.batch_trace)
         return
 
     w = workloads.CAVITY_1024x512_F32
@@ -655,6 +765,7 @@ def main():
                 sweep_us=round(r["sweep_us"], 2), tile=r["tile"],
                 bytes_per_node=BYTES_PER_NODE[wh.storage], diverged_at_step=r["diverged_at"],
                 roofline=roofline_of(wh, r, wh.storage))
+    promo = run_promotion() if args.hbm_steps > 0 else None
     batch = run_batch(args.batch_instances, 16) if args.batch_instances > 0 else None
     serve = (run_serve(args.serve_requests, min(args.serve_requests, 20),
                        batch["mlups"] if batch else main_res["mlups"])
@@ -696,6 +807,7 @@ def main():
                              "residual_last": comp["residual_last"],
                              "diverged_at_step": comp["diverged_at"]},
         "hbm_grids": big or None,
+        "precision_promotion": promo,
         "batched_solves": batch,
         "serving": serve,
         "oracle_parity": parity,

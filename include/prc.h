@@ -193,6 +193,26 @@ prc_status prc_residual(const prc_params *p, const void *f, double *u_prev,
 prc_status prc_residual_noalloc(const prc_params *p, const void *f, double *u_prev,
                                 double out[4], hipStream_t stream);
 
+/* The state f of problem *p (storage p->storage) in storage type storage_to,
+ * written to f_to (device, prc_state_bytes of *p with storage_to, 256-byte
+ * aligned, distinct from f), each in its own layout.  Deviations stay
+ * deviations; widening (FP16/BF16 -> FP32 -> FP64) is exact, narrowing
+ * rounds to nearest.  This is how a run started in 16-bit storage continues
+ * in FP32 once the 16-bit residual has reached its floor: the velocity
+ * snapshot of prc_residual does not depend on the storage and carries over.
+ * Padding of f_to is not written. */
+prc_status prc_convert(const prc_params *p, const void *f, int32_t storage_to, void *f_to,
+                       hipStream_t stream);
+
+/* Add drho * w_a to every population deviation of state f (w_a the rest
+ * weights of the layout notes above): the density of every node changes by
+ * drho and nothing else does (no momentum, the second moments of a fluid at
+ * rest).  The collision conserves mass exactly, so a run keeps the mass it
+ * starts with; rounding to 16-bit storage does not, and a run that goes on
+ * in FP32 after a 16-bit phase restores the initial mass this way (drho =
+ * (initial mass - mass) / (nx ny), the mass from prc_residual). */
+prc_status prc_add_density(const prc_params *p, void *f, double drho, hipStream_t stream);
+
 /* Hydrodynamic fields of state f (eq. hydrodynamicfields after streaming):
  * rho, u_x, u_y as device double[ny][nx] arrays (row j at offset j * nx).
  * Any of the three output pointers may be NULL. */

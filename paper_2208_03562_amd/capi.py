@@ -100,6 +100,8 @@ _PROTOS = {
     "prc_step": (ctypes.c_int, [_P, _VP, _VP, ctypes.c_int64, _VP]),
     "prc_residual": (ctypes.c_int, [_P, _VP, _DP, _VP, ctypes.POINTER(ctypes.c_double), _VP]),
     "prc_residual_noalloc": (ctypes.c_int, [_P, _VP, _DP, ctypes.POINTER(ctypes.c_double), _VP]),
+    "prc_convert": (ctypes.c_int, [_P, _VP, ctypes.c_int32, _VP, _VP]),
+    "prc_add_density": (ctypes.c_int, [_P, _VP, ctypes.c_double, _VP]),
     "prc_macros": (ctypes.c_int, [_P, _VP, _DP, _DP, _DP, _VP]),
     "prc_solve": (ctypes.c_int, [_P, _VP, _VP, _DP, _VP, ctypes.c_double, ctypes.c_int64,
                                  ctypes.c_int64, _I64P, ctypes.POINTER(ctypes.c_double),
@@ -233,6 +235,14 @@ def prc_residual_noalloc(p: prc_params, f: int, u_prev: int, stream: int = 0):
     _check("prc_residual_noalloc",
            lib().prc_residual_noalloc(ctypes.byref(p), f, u_prev, out, stream))
     return list(out)
+
+
+def prc_convert(p: prc_params, f: int, storage_to: int, f_to: int, stream: int = 0) -> None:
+    _check("prc_convert", lib().prc_convert(ctypes.byref(p), f, int(storage_to), f_to, stream))
+
+
+def prc_add_density(p: prc_params, f: int, drho: float, stream: int = 0) -> None:
+    _check("prc_add_density", lib().prc_add_density(ctypes.byref(p), f, float(drho), stream))
 
 
 def prc_macros(p: prc_params, f: int, rho: int | None, ux: int | None, uy: int | None,

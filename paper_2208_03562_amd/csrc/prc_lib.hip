@@ -57,6 +57,51 @@ __global__ void k_macros(const ST *__restrict__ f, const Coef<typename Mem<ST>::
 }
 
 
+// The state of an nx x ny grid from one storage type and layout into
+// another (grid-stride over population planes, rows, nodes); each value goes
+// through the wider of the two compute types, so widening is exact.
+template <typename SRC, typename DST>
+__global__ void k_convert(const SRC *__restrict__ src, DST *__restrict__ dst, int nx, int ny,
+                          uint32_t s_row, uint32_t s_plane, uint32_t s_bytes, uint32_t d_row,
+                          uint32_t d_plane, uint32_t d_bytes)
+{
+    const rsrc_t rs = make_rsrc(src, s_bytes), rd = make_rsrc(dst, d_bytes);
+    const int64_t n = (int64_t)9 * nx * ny;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(k % nx);
+        const int64_t q = k / nx;
+        const int j = (int)(q % ny), a = (int)(q / ny);
+        const auto v = Mem<SRC>::ld(rs, (uint32_t)a * s_plane + (uint32_t)j * s_row +
+                                            (uint32_t)i * (uint32_t)sizeof(SRC), 0);
+        Mem<DST>::st(rd, (uint32_t)a * d_plane + (uint32_t)j * d_row + (uint32_t)i * (uint32_t)sizeof(DST),
+                     0, (typename Mem<DST>::CT)v);
+    }
+}
+
+// Nine per-population constants passed by value.
+template <typename CT>
+struct Nine {
+    CT v[9];
+};
+
+// Adds delta.v[a] to population a of every node of the state (grid-stride).
+template <typename ST>
+__global__ void k_add_rest(ST *__restrict__ f, int nx, int ny, uint32_t row, uint32_t plane,
+                           uint32_t bytes, const Nine<typename Mem<ST>::CT> delta)
+{
+    const rsrc_t r = make_rsrc(f, bytes);
+    const int64_t n = (int64_t)9 * nx * ny;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(k % nx);
+        const int64_t q = k / nx;
+        const int j = (int)(q % ny), a = (int)(q / ny);
+        const uint32_t o = (uint32_t)a * plane + (uint32_t)j * row + (uint32_t)i * (uint32_t)sizeof(ST);
+        Mem<ST>::st(r, o, 0, Mem<ST>::ld(r, o, 0) + delta.v[a]);
+    }
+}
+
 // zero fill of n 16-byte words (grid-stride)
 __global__ void k_zero(uint4 *__restrict__ p, size_t n)
 {
@@ -195,6 +240,63 @@ static prc_status launch_residual(const prc_params &p, const void *f, double *u_
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_finish<>, dim3(1), dim3(kRedBlock), 0, s, (const double *)scratch, nb,
                        scratch + 4 * kRedMaxBlocks);
+    HIP_TRY(hipGetLastError());
+    return PRC_OK;
+}
+
+template <typename SRC, typename DST>
+static prc_status launch_convert_to(const prc_params &pf, const void *f, const prc_params &pt,
+                                    void *g, hipStream_t s)
+{
+    int64_t sr, sp, st_, dr, dp, dt;
+    layout(pf, sr, sp, st_);
+    layout(pt, dr, dp, dt);
+    const int64_t n = (int64_t)9 * pf.nx * pf.ny;
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL((k_convert<SRC, DST>), dim3(blocks), dim3(256), 0, s, (const SRC *)f,
+                       (DST *)g, pf.nx, pf.ny, (uint32_t)(sr * sizeof(SRC)),
+                       (uint32_t)(sp * sizeof(SRC)), (uint32_t)(st_ * sizeof(SRC)),
+                       (uint32_t)(dr * sizeof(DST)), (uint32_t)(dp * sizeof(DST)),
+                       (uint32_t)(dt * sizeof(DST)));
+    HIP_TRY(hipGetLastError());
+    return PRC_OK;
+}
+
+template <typename SRC>
+static prc_status launch_convert(const prc_params &pf, const void *f, const prc_params &pt, void *g,
+                                 hipStream_t s)
+{
+    switch (pt.storage) {
+    case PRC_F64: return launch_convert_to<SRC, double>(pf, f, pt, g, s);
+    case PRC_F32: return launch_convert_to<SRC, float>(pf, f, pt, g, s);
+    case PRC_F16: return launch_convert_to<SRC, __half>(pf, f, pt, g, s);
+    case PRC_BF16: return launch_convert_to<SRC, __hip_bfloat16>(pf, f, pt, g, s);
+    }
+    return fail(PRC_EINVAL, "bad storage %d", pt.storage);
+}
+
+template <typename ST, int BC>
+static prc_status launch_add_rest(const prc_params &p, void *f, double drho, hipStream_t s)
+{
+    using CT = typename Mem<ST>::CT;
+    // rest weights: products of the one-dimensional weights of variance c2
+    // along x and c2 / r^2 along y (velocity order of Sec. 2)
+    static const int EXh[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    static const int EYh[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    const double c2 = lattice_c2(p.r), vy = c2 / (p.r * p.r);
+    Nine<CT> d;
+    for (int a = 0; a < 9; ++a) {
+        const double wx = EXh[a] == 0 ? 1.0 - c2 : 0.5 * c2;
+        const double wy = EYh[a] == 0 ? 1.0 - vy : 0.5 * vy;
+        d.v[a] = (CT)(drho * wx * wy);
+    }
+    int64_t row, plane, total;
+    layout(p, row, plane, total);
+    const int64_t n = (int64_t)9 * p.nx * p.ny;
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL((k_add_rest<ST>), dim3(blocks), dim3(256), 0, s, (ST *)f, p.nx, p.ny,
+                       (uint32_t)(row * sizeof(ST)), (uint32_t)(plane * sizeof(ST)),
+                       (uint32_t)(total * sizeof(ST)), d);
     HIP_TRY(hipGetLastError());
     return PRC_OK;
 }
@@ -473,6 +575,34 @@ prc_status prc_residual_noalloc(const prc_params *p, const void *f, double *u_pr
     double *sc = nullptr;
     if ((st = static_scratch(&sc)) != PRC_OK) return st;
     return residual_into(*p, f, u_prev, sc, out, stream);
+}
+
+prc_status prc_convert(const prc_params *p, const void *f, int32_t storage_to, void *f_to,
+                       hipStream_t stream)
+{
+    prc_status st = validate(p);
+    if (st != PRC_OK) return st;
+    prc_params q = *p;
+    q.storage = storage_to;
+    if ((st = validate(&q)) != PRC_OK) return st;
+    if ((st = check_buf(f, "f")) != PRC_OK || (st = check_buf(f_to, "f_to")) != PRC_OK) return st;
+    if (f == f_to) return fail(PRC_EINVAL, "f and f_to must be distinct buffers");
+    switch (p->storage) {
+    case PRC_F64: return launch_convert<double>(*p, f, q, f_to, stream);
+    case PRC_F32: return launch_convert<float>(*p, f, q, f_to, stream);
+    case PRC_F16: return launch_convert<__half>(*p, f, q, f_to, stream);
+    case PRC_BF16: return launch_convert<__hip_bfloat16>(*p, f, q, f_to, stream);
+    }
+    return fail(PRC_EINVAL, "bad storage %d", p->storage);
+}
+
+prc_status prc_add_density(const prc_params *p, void *f, double drho, hipStream_t stream)
+{
+    prc_status st = validate(p);
+    if (st != PRC_OK) return st;
+    if ((st = check_buf(f, "f")) != PRC_OK) return st;
+    if (!std::isfinite(drho)) return fail(PRC_EINVAL, "drho must be finite");
+    return PRC_DISPATCH(*p, launch_add_rest, *p, f, drho, stream);
 }
 
 prc_status prc_macros(const prc_params *p, const void *f, double *rho, double *ux, double *uy,

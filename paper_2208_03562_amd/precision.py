@@ -32,6 +32,56 @@ def lid():
     return MA * min(1.0, R) / math.sqrt(3.0)
 
 
+def rel_residual(out) -> float:
+    """sqrt(sum |du|^2 / sum |u|^2); non-finite whenever a sum is (never 0 for NaN)."""
+    if out[1] > 0:
+        return math.sqrt(out[0] / out[1])
+    return 0.0 if (out[1] == 0 and out[0] == 0) else math.inf
+
+
+def promoted_solve(p: capi.prc_params, tol: float, check_every: int, max_steps: int,
+                   to: int = capi.PRC_F32, patience: int = 3, restore_mass: bool = True,
+                   stream=None):
+    """A steady-state solve that starts in the 16-bit storage of p and goes on
+    in storage `to` once the 16-bit residual has reached its floor: 16-bit
+    steps with a check every check_every steps until the residual is below
+    tol (done) or has not fallen below 0.98 of its best value for `patience`
+    checks; then the state is converted (prc_convert) and prc_solve continues
+    to tol.  The collision conserves mass, 16-bit rounding does not: with
+    `restore_mass` the converted state gets back the initial mass (a uniform
+    density shift, prc_add_density) before it goes on.  Returns (status,
+    steps in 16-bit storage, total steps, residual history, the solver
+    holding the final state, relative mass change of the 16-bit phase)."""
+    sol = solver.Solver(p, stream=stream)
+    sol.residual()  # snapshot of the initial velocity
+    mass0 = p.rho0 * p.nx * p.ny
+    hist, steps, best, stall, mass = [], 0, math.inf, 0, mass0
+    while steps + check_every <= max_steps:
+        sol.step(check_every)
+        steps += check_every
+        out = sol.residual()
+        mass = out[2]
+        Rk = rel_residual(out)
+        hist.append(Rk)
+        if not math.isfinite(Rk):
+            return capi.PRC_EDIVERGED, steps, steps, hist, sol, mass / mass0 - 1
+        if Rk < tol:
+            return capi.PRC_OK, steps, steps, hist, sol, mass / mass0 - 1
+        if Rk < 0.98 * best:
+            best, stall = Rk, 0
+        else:
+            stall += 1
+        if stall >= patience:
+            break
+    wide = sol.converted(to)
+    del sol
+    if restore_mass:
+        capi.prc_add_density(wide.p, wide.current().data_ptr(), (mass0 - mass) / (p.nx * p.ny),
+                             wide.s)
+    st, n, h = wide.solve(tol, check_every, max_steps - steps)
+    return st, steps, steps + n, hist + list(h), wide, mass / mass0 - 1
+
+
 def velocity(sol):
     _, ux, uy = sol.macros()
     return ux.cpu().numpy(), uy.cpu().numpy()

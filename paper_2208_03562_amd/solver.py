@@ -104,6 +104,18 @@ class Solver:
         return capi.prc_residual(self.p, self.current().data_ptr(), self.u_prev.data_ptr(),
                                  self.scratch.data_ptr(), self.s)
 
+    def converted(self, storage: int) -> "Solver":
+        """A new solver for the same problem in another storage type, holding
+        this solver's current state (prc_convert) and velocity snapshot, on
+        the same stream."""
+        q = self.p.copy()
+        q.storage = storage
+        out = Solver(q, device=self.device, stream=self.stream)
+        capi.prc_convert(self.p, self.current().data_ptr(), storage, out.fa.data_ptr(), self.s)
+        with torch.cuda.stream(self.stream):
+            out.u_prev.copy_(self.u_prev)
+        return out
+
     def solve(self, tol: float, check_every: int, max_steps: int):
         """Run from the current state; returns (status, steps taken, history)."""
         fa, fb = self.current(), self.other()
