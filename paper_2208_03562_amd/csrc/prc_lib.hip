@@ -112,14 +112,24 @@ __global__ void k_zero(uint4 *__restrict__ p, size_t n)
 
 // Tile shape per problem: what prc_tune measured for this grid, else a
 // default (wide tiles for wide grids); PRC_TILE=<index> forces one shape.
+// storage, boundary type, grid and layout mode of a problem
+struct TuneKey {
+    int32_t nx, ny, mode;
+    bool operator==(const TuneKey &o) const { return nx == o.nx && ny == o.ny && mode == o.mode; }
+};
+struct TuneKeyHash {
+    size_t operator()(const TuneKey &k) const
+    {
+        return std::hash<uint64_t>()(((uint64_t)(uint32_t)k.nx << 32) ^ (uint64_t)(uint32_t)k.ny ^
+                                     ((uint64_t)(uint32_t)k.mode << 48));
+    }
+};
 static std::mutex g_tune_mu;
-static std::unordered_map<std::string, int> g_tuned;
+static std::unordered_map<TuneKey, int, TuneKeyHash> g_tuned;
 
-static std::string tune_key(const prc_params &p)
+static TuneKey tune_key(const prc_params &p)
 {
-    char k[96];
-    std::snprintf(k, sizeof k, "%d/%d/%d/%d/%d", p.storage, p.bc, p.nx, p.ny, layout_mode());
-    return k;
+    return TuneKey{p.nx, p.ny, (p.storage * 3 + p.bc) * 3 + layout_mode()};
 }
 
 static int tile_choice(const prc_params &p)
@@ -191,10 +201,10 @@ static int single_step_tile(int tile)
 // fours from an even step and leave every state a caller can see on the
 // buffer the single-step sequence puts it in; single steps do the rest.
 static prc_status run_steps(const prc_params &p, int tile, void *f_a, void *f_b, int64_t k0,
-                            int64_t n, hipStream_t s)
+                            int64_t n, hipStream_t s, int capturing = -1)
 {
     if (tile == kResidentTile)  // any number of steps per launch
-        return launch_resident(p, (k0 & 1) ? f_b : f_a, (k0 & 1) ? f_a : f_b, n, s);
+        return launch_resident(p, (k0 & 1) ? f_b : f_a, (k0 & 1) ? f_a : f_b, n, s, capturing);
     prc_status st = PRC_OK;
     int64_t k = k0;
     const int64_t end = k0 + n;
@@ -549,7 +559,8 @@ prc_status prc_step(const prc_params *p, void *f_a, void *f_b, int64_t nsteps, h
         if ((st = get_graph(*p, tile, f_a, f_b, gsteps, &g)) != PRC_OK) return st;
         for (; k + gsteps <= nsteps; k += gsteps) HIP_TRY(hipGraphLaunch(g->exec, stream));
     }
-    return run_steps(*p, tile, f_a, f_b, k, nsteps - k, stream);
+    return run_steps(*p, tile, f_a, f_b, k, nsteps - k, stream,
+                     cap == hipStreamCaptureStatusNone ? 0 : 1);
 }
 
 prc_status prc_residual(const prc_params *p, const void *f, double *u_prev, void *scratch,

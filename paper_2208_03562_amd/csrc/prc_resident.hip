@@ -150,16 +150,20 @@ prc_status resident_prepare(hipStream_t s)
 }
 
 prc_status launch_resident(const prc_params &p, const void *src, void *dst, int64_t nsteps,
-                           hipStream_t s)
+                           hipStream_t s, int capturing)
 {
-    if (!resident_allowed(p))
-        return fail(PRC_EINVAL, "the resident sweep cannot run a %d x %d grid of storage %d",
-                    p.nx, p.ny, p.storage);
     ResidentDevice *d = nullptr;
     prc_status st = current_device(&d);
     if (st != PRC_OK) return st;
+    if (p.storage == PRC_F64 || (size_t)d->lds < resident_lds_bytes(p.storage) ||
+        resident_tiles(p) > d->cus || resident_tiles(p) > kResidentMaxGroups ||
+        (p.bc != PRC_BC_CAVITY && p.nx % kResidentSX != 0) ||
+        (p.bc == PRC_BC_PERIODIC && p.ny % kResidentSY != 0))
+        return fail(PRC_EINVAL, "the resident sweep cannot run a %d x %d grid of storage %d",
+                    p.nx, p.ny, p.storage);
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    HIP_TRY(hipStreamIsCapturing(s, &cap));
+    if (capturing < 0) HIP_TRY(hipStreamIsCapturing(s, &cap));
+    else cap = capturing ? hipStreamCaptureStatusActive : hipStreamCaptureStatusNone;
     std::lock_guard<std::mutex> lock(g_res_mu);
     if (!d->sync) return fail(PRC_EHIP, "resident sweep: flags not set up on this device");
     // a launch on another stream than the latest one waits for that one
