@@ -49,37 +49,36 @@ def run_gpu(w: workloads.Cavity, steps: int, warmup: int):
     from paper_2208_03562_amd import capi
     tile = capi.prc_tune(p, stream.cuda_stream)  # autotuned tile shape (untimed)
     sol = solver.Solver(p, device="cuda:0", stream=stream)
-    sol.residual()  # velocity snapshot of the initial state
-    diverged_at = None
-    done = 0
-    while done < warmup:
-        n = min(CHECK_EVERY, warmup - done)
-        sol.step(n)
-        done += n
-        if done % CHECK_EVERY == 0:
-            out = sol.residual()
-            R = rel_residual(out)
-            if diverged_at is None and not (math.isfinite(R) and out[3] < 1.0):
-                diverged_at = done
-    log(f"[bench] {w.name}: warmup {warmup} steps done")
-
-    # one pair of HIP events per chunk of at most CHECK_EVERY steps, on the
-    # solver's stream; created and recorded once before the timed region (a
-    # torch event creates its HIP event at its first record)
+    # one pair of HIP events per chunk of at most CHECK_EVERY steps, recorded
+    # on the solver's stream around the chunk by the library
+    # (prc_step_timed); created and recorded once before the warm-up (a torch
+    # event creates its HIP event at its first record), so that the timed
+    # region follows the warm-up directly
     chunks = [min(CHECK_EVERY, steps - k) for k in range(0, steps, CHECK_EVERY)]
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in chunks]
     for a, b in ev:
         a.record(stream)
         b.record(stream)
+    sol.residual()  # velocity snapshot of the initial state
+    diverged_at = None
+    done = 0
+    while done < warmup:
+        n = min(CHECK_EVERY, warmup - done)
+        # (through the timed region's call and events: its code paths are warm)
+        sol.step_timed(n, *ev[0])
+        done += n
+        if done % CHECK_EVERY == 0:
+            out = sol.residual()
+            R = rel_residual(out)
+            if diverged_at is None and not (math.isfinite(R) and out[3] < 1.0):
+                diverged_at = done
     hist = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     done = 0
     for (a, b), n in zip(ev, chunks):
-        a.record(stream)
-        sol.step(n)
-        b.record(stream)
+        sol.step_timed(n, a, b)  # events recorded by the library around the chunk
         done += n
         if done % CHECK_EVERY == 0:
             out = sol.residual()  # synchronises the stream
@@ -89,6 +88,7 @@ def run_gpu(w: workloads.Cavity, steps: int, warmup: int):
                 diverged_at = warmup + done
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    log(f"[bench] {w.name}: warmup {warmup} steps, then {steps} timed")
     # a resident launch that lost a wait would have produced an invalid state
     try:
         capi.prc_resident_status()
@@ -96,6 +96,14 @@ def run_gpu(w: workloads.Cavity, steps: int, warmup: int):
     except capi.PrcError:
         resident_ok = False
     chunk_ms = [a.elapsed_time(b) for a, b in ev]
+    # kernel time alone of one more call of the first chunk's length, after
+    # the timed region: events recorded by the launch itself (prc_step_timed;
+    # for the resident sweep the dispatch's own start and end, the duration a
+    # kernel trace reports)
+    ka, kb = ev[0]
+    sol.step_timed(chunks[0], ka, kb, kernel_only=True)
+    torch.cuda.synchronize()
+    kernel_only_us = 1e3 * ka.elapsed_time(kb)
     nodes = w.nx * w.ny
     wall = t1 - t0
     full = [m for m, n in zip(chunk_ms, chunks) if n == chunks[0]]
@@ -107,6 +115,7 @@ def run_gpu(w: workloads.Cavity, steps: int, warmup: int):
         # the first chunk's size and the mean event time of the chunks of that size
         chunk_steps=chunks[0],
         chunk_us=1e3 * sum(full) / len(full),
+        chunk_kernel_us=kernel_only_us,
         resident_ok=resident_ok,
         residual_last=(hist[-1] if math.isfinite(hist[-1]) else str(hist[-1])) if hist else None,
         diverged_at=diverged_at,
@@ -218,11 +227,17 @@ def run_serve(n_req: int, solo_req: int, mlups_hint: float):
     on = serving.serve_online(ps, arrivals, **kw)
     s_on = serving.summary(on)
     log(f"[bench] serving {n_req} requests at {lam:.2f}/s: {s_on}")
+    # the first solo_req requests alone, batched and one at a time: the same
+    # arrivals and the same load for both
+    few = serving.serve_online(ps[:solo_req], arrivals[:solo_req], **kw)
+    s_few = serving.summary(few)
     one = serving.serve_online(ps[:solo_req], arrivals[:solo_req], max_active=1, **kw)
     s_one = serving.summary(one)
     s_on_head = serving.summary(on[:solo_req])
+    log(f"[bench] first {solo_req} batched: {s_few}")
     log(f"[bench] first {solo_req} one at a time: {s_one}")
-    same = all((a.status, a.steps) == (b.status, b.steps) for a, b in zip(on, one))
+    same = all((a.status, a.steps) == (b.status, b.steps) == (c.status, c.steps)
+               for a, b, c in zip(on, one, few))
     rnd = lambda d: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}  # noqa
     return {
         "workload": f"{n_req} requests, Poisson arrivals (seed 1) at {lam:.3f}/s; Nx log-uniform "
@@ -231,8 +246,9 @@ def run_serve(n_req: int, solo_req: int, mlups_hint: float):
         "rate_per_s": round(lam, 4), "hbm_budget_bytes": budget,
         "interface": "online server: each request submitted at its arrival time, results polled",
         "batched": rnd(s_on),
-        "batched_first": rnd(s_on_head),
-        "one_at_a_time_first": rnd(s_one),
+        "batched_first_in_full_trace": rnd(s_on_head),
+        "batched_first_alone": rnd(s_few),
+        "one_at_a_time_first_alone": rnd(s_one),
         "same_steps_and_status_alone": same,
     }
 
@@ -668,6 +684,7 @@ def roofline_of(w: workloads.Cavity, res: dict, storage: str):
     alg = BYTES_PER_NODE[storage] * nodes * per_launch
     c = measured_counters(w, kernel, per_launch)
     rec = {"kernel": kernel, "steps_per_launch": per_launch, "kernel_us": round(kernel_us, 3),
+           "kernel_only_us": round(res["chunk_kernel_us"] / (res["chunk_steps"] / per_launch), 3),
            "algorithmic_bytes": alg,
            "algorithmic_gbs": round(alg / (kernel_us * 1e-6) / 1e9, 1),
            "algorithmic_frac": round(alg / (kernel_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
@@ -817,9 +834,13 @@ def main():
 
 
 STEADY_STEPS, STEADY_WARMUP = 12000, 2000
-ROOFLINE_NOTE = ("kernel_us: HIP events on the solver's stream around the timed launch (the "
-                 "resident sweep runs a chunk of steps as one launch; other shapes: the mean "
-                 "over the chunk's launches).  traffic: HBM bytes per launch from the committed "
+ROOFLINE_NOTE = ("kernel_us: HIP events recorded on the solver's stream around the timed "
+                 "chunk by prc_step_timed (the resident sweep runs a chunk as one launch; other "
+                 "shapes: the mean "
+                 "over the chunk's launches); it includes the dispatch.  kernel_only_us: one "
+                 "more call of the same length after the timed region, its events recorded by "
+                 "the launch itself (prc_step_timed: the resident sweep's dispatch), the "
+                 "duration a kernel trace reports.  traffic: HBM bytes per launch from the committed "
                  "FETCH_SIZE + WRITE_SIZE counters of this instance at this launch length, each "
                  "scaled by its reading for a 256 MiB copy; null if the code changed since.  "
                  "bound/frac: the measured resource with the larger fraction -- HBM bytes "

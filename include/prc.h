@@ -161,6 +161,18 @@ prc_status prc_init(const prc_params *p, void *f, hipStream_t stream);
 prc_status prc_step(const prc_params *p, void *f_a, void *f_b, int64_t nsteps,
                     hipStream_t stream);
 
+/* prc_step, timed: start and stop (events created by the caller, e.g. with
+ * hipEventCreate; timing enabled) are recorded on `stream` before and after
+ * the call's work.  With kernel_only set, the resident sweep's dispatch
+ * records them itself (hipExtLaunchKernel): start when the first launch of
+ * the call begins, stop when its last launch ends, so hipEventElapsedTime
+ * gives kernel time alone (as a kernel trace reports it; such a launch takes
+ * longer to dispatch); other shapes record them around the call either way.
+ * PRC_EINVAL if either event is NULL. */
+prc_status prc_step_timed(const prc_params *p, void *f_a, void *f_b, int64_t nsteps,
+                          hipEvent_t start, hipEvent_t stop, int32_t kernel_only,
+                          hipStream_t stream);
+
 /* Convergence check (Sec. 5.2: L2 norm of the change of the velocity between
  * checks).  Computes, in double precision, from the fields of state f:
  *   out[0] = sum_nodes |u - u_prev|^2     out[1] = sum_nodes |u|^2

@@ -98,6 +98,8 @@ _PROTOS = {
     "prc_scratch_bytes": (ctypes.c_size_t, [_P]),
     "prc_init": (ctypes.c_int, [_P, _VP, _VP]),
     "prc_step": (ctypes.c_int, [_P, _VP, _VP, ctypes.c_int64, _VP]),
+    "prc_step_timed": (ctypes.c_int, [_P, _VP, _VP, ctypes.c_int64, _VP, _VP, ctypes.c_int32,
+                                      _VP]),
     "prc_residual": (ctypes.c_int, [_P, _VP, _DP, _VP, ctypes.POINTER(ctypes.c_double), _VP]),
     "prc_residual_noalloc": (ctypes.c_int, [_P, _VP, _DP, ctypes.POINTER(ctypes.c_double), _VP]),
     "prc_convert": (ctypes.c_int, [_P, _VP, ctypes.c_int32, _VP, _VP]),
@@ -222,6 +224,12 @@ def prc_init(p: prc_params, f: int, stream: int = 0) -> None:
 
 def prc_step(p: prc_params, f_a: int, f_b: int, nsteps: int, stream: int = 0) -> None:
     _check("prc_step", lib().prc_step(ctypes.byref(p), f_a, f_b, int(nsteps), stream))
+
+
+def prc_step_timed(p: prc_params, f_a: int, f_b: int, nsteps: int, start: int, stop: int,
+                   kernel_only: bool = False, stream: int = 0) -> None:
+    _check("prc_step_timed", lib().prc_step_timed(ctypes.byref(p), f_a, f_b, nsteps, start, stop,
+                                                  int(bool(kernel_only)), stream))
 
 
 def prc_residual(p: prc_params, f: int, u_prev: int, scratch: int, stream: int = 0):

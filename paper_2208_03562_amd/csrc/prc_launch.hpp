@@ -71,9 +71,12 @@ prc_status launch_sweep_wide(const prc_params &p, int tile, const void *src, voi
 // and the release of the device's resident buffers (after a device
 // synchronise).
 prc_status resident_prepare(hipStream_t s);
-// (capturing: whether s is under graph capture, -1 to ask the runtime)
+// (capturing: whether s is under graph capture, -1 to ask the runtime;
+// start/stop, if given, are recorded by the dispatch of the first and the
+// last kernel: the start of the first, the end of the last)
 prc_status launch_resident(const prc_params &p, const void *src, void *dst, int64_t nsteps,
-                           hipStream_t s, int capturing = -1);
+                           hipStream_t s, int capturing = -1, hipEvent_t start = nullptr,
+                           hipEvent_t stop = nullptr);
 prc_status resident_report();
 prc_status resident_release();
 // wait limit of later resident launches, in 100 MHz ticks (-1: the default)

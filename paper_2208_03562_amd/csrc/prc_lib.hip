@@ -201,10 +201,12 @@ static int single_step_tile(int tile)
 // fours from an even step and leave every state a caller can see on the
 // buffer the single-step sequence puts it in; single steps do the rest.
 static prc_status run_steps(const prc_params &p, int tile, void *f_a, void *f_b, int64_t k0,
-                            int64_t n, hipStream_t s, int capturing = -1)
+                            int64_t n, hipStream_t s, int capturing = -1,
+                            hipEvent_t start = nullptr, hipEvent_t stop = nullptr)
 {
     if (tile == kResidentTile)  // any number of steps per launch
-        return launch_resident(p, (k0 & 1) ? f_b : f_a, (k0 & 1) ? f_a : f_b, n, s, capturing);
+        return launch_resident(p, (k0 & 1) ? f_b : f_a, (k0 & 1) ? f_a : f_b, n, s, capturing,
+                               start, stop);
     prc_status st = PRC_OK;
     int64_t k = k0;
     const int64_t end = k0 + n;
@@ -532,7 +534,28 @@ prc_status prc_init(const prc_params *p, void *f, hipStream_t stream)
     return PRC_OK;
 }
 
+static prc_status step_impl(const prc_params *p, void *f_a, void *f_b, int64_t nsteps,
+                            hipEvent_t start, hipEvent_t stop, hipStream_t stream);
+
 prc_status prc_step(const prc_params *p, void *f_a, void *f_b, int64_t nsteps, hipStream_t stream)
+{
+    return step_impl(p, f_a, f_b, nsteps, nullptr, nullptr, stream);
+}
+
+prc_status prc_step_timed(const prc_params *p, void *f_a, void *f_b, int64_t nsteps,
+                          hipEvent_t start, hipEvent_t stop, int32_t kernel_only,
+                          hipStream_t stream)
+{
+    if (!start || !stop) return fail(PRC_EINVAL, "NULL start or stop event");
+    if (kernel_only) return step_impl(p, f_a, f_b, nsteps, start, stop, stream);
+    HIP_TRY(hipEventRecord(start, stream));
+    const prc_status st = step_impl(p, f_a, f_b, nsteps, nullptr, nullptr, stream);
+    if (st == PRC_OK) HIP_TRY(hipEventRecord(stop, stream));
+    return st;
+}
+
+static prc_status step_impl(const prc_params *p, void *f_a, void *f_b, int64_t nsteps,
+                            hipEvent_t start, hipEvent_t stop, hipStream_t stream)
 {
     prc_status st = validate(p);
     if (st != PRC_OK) return st;
@@ -552,15 +575,21 @@ prc_status prc_step(const prc_params *p, void *f_a, void *f_b, int64_t nsteps, h
     const int gsteps = graph_steps();
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     HIP_TRY(hipStreamIsCapturing(stream, &cap));
+    const int capturing = cap == hipStreamCaptureStatusNone ? 0 : 1;
+    // timed calls: the resident sweep's dispatch records the events itself
+    // (the kernel's own start and end); other shapes bracket the call
+    if (tile == kResidentTile && nsteps > 0)
+        return run_steps(*p, tile, f_a, f_b, 0, nsteps, stream, capturing, start, stop);
+    if (start) HIP_TRY(hipEventRecord(start, stream));
     // (the resident sweep takes any number of steps in one launch: no graph)
-    if (tile != kResidentTile && gsteps > 0 && cap == hipStreamCaptureStatusNone &&
-        nsteps >= 2 * gsteps) {
+    if (tile != kResidentTile && gsteps > 0 && !capturing && nsteps >= 2 * gsteps) {
         std::shared_ptr<GraphEntry> g;  // held while replaying
         if ((st = get_graph(*p, tile, f_a, f_b, gsteps, &g)) != PRC_OK) return st;
         for (; k + gsteps <= nsteps; k += gsteps) HIP_TRY(hipGraphLaunch(g->exec, stream));
     }
-    return run_steps(*p, tile, f_a, f_b, k, nsteps - k, stream,
-                     cap == hipStreamCaptureStatusNone ? 0 : 1);
+    st = run_steps(*p, tile, f_a, f_b, k, nsteps - k, stream, capturing);
+    if (st == PRC_OK && stop) HIP_TRY(hipEventRecord(stop, stream));
+    return st;
 }
 
 prc_status prc_residual(const prc_params *p, const void *f, double *u_prev, void *scratch,

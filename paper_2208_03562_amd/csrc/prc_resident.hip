@@ -3,6 +3,7 @@
 // (serialised across streams), the report of an aborted wait, and the
 // release of the per-device resources.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <atomic>
 #include <mutex>
@@ -73,7 +74,7 @@ int resident_tiles(const prc_params &p)
 
 template <typename ST, int BC>
 prc_status launch_res(const prc_params &p, const void *src, void *dst, int nsteps,
-                      const ResidentDevice &d, hipStream_t s)
+                      const ResidentDevice &d, hipStream_t s, hipEvent_t start, hipEvent_t stop)
 {
     if constexpr (sizeof(ST) > 4) {  // an FP64 subdomain does not fit the LDS
         return fail(PRC_EINVAL, "the resident sweep has no FP64 instance");
@@ -84,12 +85,13 @@ prc_status launch_res(const prc_params &p, const void *src, void *dst, int nstep
     c.tiles_per_xcd = (c.tiles_x * c.tiles_y + kXcds - 1) / kXcds;
     const dim3 grid(c.tiles_per_xcd * kXcds), block(kResidentThreads);
     const uint64_t wait = g_wait_ticks.load(std::memory_order_relaxed);
-    if (is_plain_method(p))
-        hipLaunchKernelGGL((k_resident<ST, BC, false, true>), grid, block, 0, s, (ST *)src,
-                           (ST *)dst, d.xch, c, d.sync, (uint64_t *)d.mailbox, wait, nsteps);
+    auto kern = is_plain_method(p) ? k_resident<ST, BC, false, true> : k_resident<ST, BC, true, false>;
+    if (start || stop)  // events taken by the dispatch itself: the kernel's own start and end
+        hipExtLaunchKernelGGL(kern, grid, block, 0, s, start, stop, 0, (ST *)src, (ST *)dst, d.xch,
+                              c, d.sync, (uint64_t *)d.mailbox, wait, nsteps);
     else
-        hipLaunchKernelGGL((k_resident<ST, BC, true, false>), grid, block, 0, s, (ST *)src,
-                           (ST *)dst, d.xch, c, d.sync, (uint64_t *)d.mailbox, wait, nsteps);
+        hipLaunchKernelGGL(kern, grid, block, 0, s, (ST *)src, (ST *)dst, d.xch, c, d.sync,
+                           (uint64_t *)d.mailbox, wait, nsteps);
     HIP_TRY(hipGetLastError());
     return PRC_OK;
     }
@@ -150,7 +152,7 @@ prc_status resident_prepare(hipStream_t s)
 }
 
 prc_status launch_resident(const prc_params &p, const void *src, void *dst, int64_t nsteps,
-                           hipStream_t s, int capturing)
+                           hipStream_t s, int capturing, hipEvent_t start, hipEvent_t stop)
 {
     ResidentDevice *d = nullptr;
     prc_status st = current_device(&d);
@@ -171,9 +173,13 @@ prc_status launch_resident(const prc_params &p, const void *src, void *dst, int6
     const bool track = cap == hipStreamCaptureStatusNone;
     if (track && d->has_last && d->last_stream != s) HIP_TRY(hipStreamWaitEvent(s, d->last, 0));
     void *a = const_cast<void *>(src), *b = dst;
+    bool first = true;
     while (nsteps > 0 && st == PRC_OK) {
         const int64_t n = nsteps < kResidentMaxSteps ? nsteps : kResidentMaxSteps;
-        st = PRC_DISPATCH(p, launch_res, p, a, b, (int)n, *d, s);
+        const bool last = n == nsteps;
+        st = PRC_DISPATCH(p, launch_res, p, a, b, (int)n, *d, s, first ? start : nullptr,
+                          last ? stop : nullptr);
+        first = false;
         if (n & 1) std::swap(a, b);  // an odd count leaves the state in the second buffer
         nsteps -= n;
     }

@@ -90,6 +90,15 @@ class Solver:
         capi.prc_step(self.p, self.current().data_ptr(), self.other().data_ptr(), n, self.s)
         self.steps += int(n)
 
+    def step_timed(self, n: int, start: torch.cuda.Event, stop: torch.cuda.Event,
+                   kernel_only: bool = False) -> None:
+        """step(n) with start/stop (timing events, recorded once already so
+        that their HIP events exist) recorded by the library around the work,
+        or with kernel_only by the resident sweep's dispatch itself."""
+        capi.prc_step_timed(self.p, self.current().data_ptr(), self.other().data_ptr(), n,
+                            start.cuda_event, stop.cuda_event, kernel_only, self.s)
+        self.steps += int(n)
+
     def macros(self):
         ny, nx = self.p.ny, self.p.nx
         rho = torch.empty((ny, nx), dtype=torch.float64, device=self.device)

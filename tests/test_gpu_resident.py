@@ -186,3 +186,26 @@ def test_lost_wait_is_reported_once_and_the_next_launch_is_clean():
     ref = run(small, 0, 7, seed=31)
     assert bool((run(small, RESIDENT, 7, seed=31) == ref).all())
     capi.prc_set_tile(sol.p, -1)
+
+
+@pytest.mark.parametrize("tile", [RESIDENT, 7, 0])
+def test_timed_step_gives_the_same_bits_and_a_kernel_time(tile):
+    """prc_step_timed: the same state as prc_step; its events (taken by the
+    resident sweep's dispatch, around the call for other shapes) give a
+    positive elapsed time."""
+    from paper_2208_03562_amd import capi, solver
+    s = spec(256, 128, 2.0, 0.5, omega_nu=1.3, u_lid=0.05, storage="f32")
+    ref = run(s, tile, 37, seed=5)
+    sol = solver.Solver(lib_params(s))
+    capi.prc_set_tile(sol.p, tile)
+    sol.set_state(workloads.deviation_noise(256, 128, 5, 1e-3))
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(sol.stream)
+    b.record(sol.stream)
+    sol.step_timed(20, a, b)
+    sol.step_timed(17, a, b, kernel_only=True)
+    torch.cuda.synchronize()
+    assert a.elapsed_time(b) > 0.0
+    assert bool((sol.get_state() == ref).all())
+    capi.prc_set_tile(sol.p, -1)
+    capi.prc_release_graphs()
