@@ -135,6 +135,18 @@ __device__ __forceinline__ void reflect(const Coef<CT> &c, ST (*P)[SY + 4][SX + 
     }
 }
 
+// Whether some population streams to grid node (x, y) from beyond a wall
+// (x or y next to a side that does not wrap): only such nodes have ghost
+// slots to fill.
+template <int BC>
+__device__ __forceinline__ bool beside_wall(int nx, int ny, int x, int y)
+{
+    bool w = false;
+    if (!Bc<BC>::wrap_x) w |= (x == 0) | (x == nx - 1);
+    if (!Bc<BC>::wrap_y) w |= (y == 0) | (y == ny - 1);
+    return w;
+}
+
 // One subdomain per workgroup, two nodes per thread.  Each thread owns one
 // node at least two nodes from the subdomain's boundary (an inner node) and
 // a second node that collides early for threads below L0 (another inner
@@ -226,7 +238,7 @@ __global__ void __launch_bounds__(kResidentThreads)
     // wall), that node's row (lid), and whether its sources are all the
     // subdomain's own
     int si[2], sj[2], hx[2], hy[2], ly[2];
-    bool act[2], own[2];
+    bool act[2], own[2], wall[2];
     si[0] = 2 + t % IW;
     sj[0] = 2 + t / IW;
     if (t < L0 + LI) {  // inner nodes T .. NI - 1
@@ -242,6 +254,7 @@ __global__ void __launch_bounds__(kResidentThreads)
         ly[m] = y;
         act[m] = x0 + si[m] < c.nx && y0 + sj[m] < c.ny;
         own[m] = hx[m] >= 1 && hx[m] <= SX - 2 && hy[m] >= 1 && hy[m] <= SY - 2;
+        wall[m] = act[m] && beside_wall<BC>(c.nx, c.ny, x0 + si[m], y0 + sj[m]);
     }
     // the ring slot of this thread (threads below 2 (SX + 2) + 2 SY)
     const TileGeom<SX, SY> g(t);
@@ -270,20 +283,21 @@ __global__ void __launch_bounds__(kResidentThreads)
         }
     }
     const bool qring1 = qv && qi >= -1 && qi <= SX && qj >= -1 && qj <= SY;
+    const bool qwall = qring1 && beside_wall<BC>(c.nx, c.ny, x0 + qi, y0 + qj);
 
     // ghost slots of the input state: every in-grid slot that streaming reads
     // from (own nodes, ring slots) reflects into the walls
     if (!inner) {
 #pragma unroll
         for (int m = 0; m < 2; ++m) {
-            if (act[m]) {
+            if (wall[m]) {
                 ST v[9];
 #pragma unroll
                 for (int a = 0; a < 9; ++a) v[a] = P[a][sj[m] + 2][si[m] + 2];
                 reflect<ST, BC, SX, SY>(c, P, x0, y0, si[m], sj[m], v);
             }
         }
-        if (g.ring && in_grid(g.hx, g.hy)) {
+        if (g.ring && in_grid(g.hx, g.hy) && beside_wall<BC>(c.nx, c.ny, x0 + g.hx, y0 + g.hy)) {
             ST v[9];
 #pragma unroll
             for (int a = 0; a < 9; ++a) v[a] = P[a][g.hy + 2][g.hx + 2];
@@ -365,7 +379,7 @@ __global__ void __launch_bounds__(kResidentThreads)
             for (int a = 0; a < 9; ++a) v[a] = bits_value<ST>(h[a].x);
 #pragma unroll
             for (int a = 0; a < 9; ++a) P[a][qj + 2][qi + 2] = v[a];
-            if (!inner && qring1) reflect<ST, BC, SX, SY>(c, P, x0, y0, qi, qj, v);
+            if (!inner && qwall) reflect<ST, BC, SX, SY>(c, P, x0, y0, qi, qj, v);
         }
         __syncthreads();
         if (s_abort != 0) break;
@@ -400,7 +414,7 @@ __global__ void __launch_bounds__(kResidentThreads)
             for (int a = 0; a < 9; ++a) v[a] = LdsVal<ST>::put(d[m][a]);
 #pragma unroll
             for (int a = 0; a < 9; ++a) P[a][j + 2][i + 2] = v[a];
-            if (!inner) reflect<ST, BC, SX, SY>(c, P, x0, y0, i, j, v);
+            if (!inner && wall[m]) reflect<ST, BC, SX, SY>(c, P, x0, y0, i, j, v);
             if (last) {
                 const rsrc_t ro = make_rsrc((s & 1) ? buf1 : buf0, c.state_bytes);
                 const uint32_t o = (uint32_t)(y0 + j) * c.row_bytes + (uint32_t)(x0 + i) * E;
