@@ -103,15 +103,15 @@ __device__ __forceinline__ void halo_pos(int k, int &i, int &j)
 
 // Subdomain-relative position of edge node k (the nodes within one of the
 // subdomain's boundary: two bottom rows, two top rows, then the two left and
-// two right columns between them; 4 SX + 4 (SY - 4) nodes).
+// two right columns between them, four nodes of one row after another, so
+// that the lanes of a wave fall on different LDS banks; 4 SX + 4 (SY - 4)
+// nodes).
 template <int SX, int SY>
 __device__ __forceinline__ void edge_pos(int k, int &i, int &j)
 {
-    constexpr int H = SY - 4;
     if (k < 2 * SX) { i = k % SX; j = k / SX; }
     else if (k < 4 * SX) { k -= 2 * SX; i = k % SX; j = SY - 2 + k / SX; }
-    else if (k < 4 * SX + 2 * H) { k -= 4 * SX; i = k / H; j = 2 + k % H; }
-    else { k -= 4 * SX + 2 * H; i = SX - 2 + k / H; j = 2 + k % H; }
+    else { k -= 4 * SX; const int q = k % 4; i = q < 2 ? q : SX - 4 + q; j = 2 + k / 4; }
 }
 
 // Half-way bounce-back through ghost slots: for the in-grid slot (i, j)
@@ -399,46 +399,64 @@ __global__ void __launch_bounds__(kResidentThreads)
         }
         __syncthreads();
 
-        // W: the edge nodes collide; the new state into LDS (and its ghost
-        // slots), the edges into the exchange blocks tagged with this step
-        // (every node into the output state at the last step)
-        if (t >= L0 && act[1]) collide_at(si[1], sj[1], d[1]);
+        // W: the late nodes collide; the new state into LDS (and its ghost
+        // slots), the edges into the exchange blocks tagged with this step;
+        // at the last step every node into the output state instead.  A late
+        // thread stores its edge node's values for the neighbours, who wait
+        // for them, before anything else goes into LDS.
         const uint32_t xb = (uint32_t)(((s & 1) * ntiles + sub) * kXchElems) * kXchPair;
         const uint32_t tag = (uint32_t)(base + (uint64_t)s);
-#pragma unroll
-        for (int m = 0; m < 2; ++m) {
-            if (!act[m]) continue;
+        auto put = [&](int m, const ST *v) {
             const int i = si[m], j = sj[m];
-            ST v[9];
-#pragma unroll
-            for (int a = 0; a < 9; ++a) v[a] = LdsVal<ST>::put(d[m][a]);
-#pragma unroll
-            for (int a = 0; a < 9; ++a) P[a][j + 2][i + 2] = v[a];
-            if (!inner && wall[m]) reflect<ST, BC, SX, SY>(c, P, x0, y0, i, j, v);
             if (last) {
                 const rsrc_t ro = make_rsrc((s & 1) ? buf1 : buf0, c.state_bytes);
                 const uint32_t o = (uint32_t)(y0 + j) * c.row_bytes + (uint32_t)(x0 + i) * E;
 #pragma unroll
                 for (int a = 0; a < 9; ++a) Mem<ST>::st(ro, o, a * c.plane_bytes, d[m][a]);
-            } else if (m == 1 && t >= L0 + LI) {
-                if (j < 2 || j >= SY - 2) {  // a row block
-                    const uint32_t o =
-                        xb + (uint32_t)((j < 2 ? kXchBot + j * SX : kXchTop + (j - SY + 2) * SX) + i) *
-                                 kXchPair;
-#pragma unroll
-                    for (int a = 0; a < 9; ++a)
-                        __builtin_amdgcn_raw_buffer_store_b64(pair_t{value_bits<ST>(v[a]), tag}, rx, o,
-                                                              a * kXchRowPlane * kXchPair, kAgent);
-                }
-                if (i < 2 || i >= SX - 2) {  // a column block
-                    const uint32_t o =
-                        xb + (uint32_t)((i < 2 ? kXchLeft + i : kXchRight + i - SX + 2) + 2 * j) * kXchPair;
-#pragma unroll
-                    for (int a = 0; a < 9; ++a)
-                        __builtin_amdgcn_raw_buffer_store_b64(pair_t{value_bits<ST>(v[a]), tag}, rx, o,
-                                                              a * kXchColPlane * kXchPair, kAgent);
-                }
+                return;
             }
+#pragma unroll
+            for (int a = 0; a < 9; ++a) P[a][j + 2][i + 2] = v[a];
+            if (!inner && wall[m]) reflect<ST, BC, SX, SY>(c, P, x0, y0, i, j, v);
+        };
+        auto put_node = [&](int m) {
+            ST v[9];
+#pragma unroll
+            for (int a = 0; a < 9; ++a) v[a] = LdsVal<ST>::put(d[m][a]);
+            put(m, v);
+        };
+        if (t < L0) {  // both nodes collided in Y
+            if (act[0]) put_node(0);
+            if (act[1]) put_node(1);
+        } else {
+            if (act[1]) {
+                collide_at(si[1], sj[1], d[1]);
+                const int i = si[1], j = sj[1];
+                ST v[9];
+#pragma unroll
+                for (int a = 0; a < 9; ++a) v[a] = LdsVal<ST>::put(d[1][a]);
+                if (!last && t >= L0 + LI) {
+                    if (j < 2 || j >= SY - 2) {  // a row block
+                        const uint32_t o =
+                            xb + (uint32_t)((j < 2 ? kXchBot + j * SX : kXchTop + (j - SY + 2) * SX) + i) *
+                                     kXchPair;
+#pragma unroll
+                        for (int a = 0; a < 9; ++a)
+                            __builtin_amdgcn_raw_buffer_store_b64(pair_t{value_bits<ST>(v[a]), tag}, rx, o,
+                                                                  a * kXchRowPlane * kXchPair, kAgent);
+                    }
+                    if (i < 2 || i >= SX - 2) {  // a column block
+                        const uint32_t o = xb + (uint32_t)((i < 2 ? kXchLeft + i : kXchRight + i - SX + 2) +
+                                                           2 * j) * kXchPair;
+#pragma unroll
+                        for (int a = 0; a < 9; ++a)
+                            __builtin_amdgcn_raw_buffer_store_b64(pair_t{value_bits<ST>(v[a]), tag}, rx, o,
+                                                                  a * kXchColPlane * kXchPair, kAgent);
+                    }
+                }
+                put(1, v);
+            }
+            if (act[0]) put_node(0);
         }
         __syncthreads();
     }
