@@ -63,8 +63,8 @@ prc_status current_device(ResidentDevice **out)
 size_t resident_lds_bytes(int storage)
 {
     const size_t ct = storage == PRC_F64 ? 8 : 4;
-    return elem_bytes(storage) * 9 * (kResidentSY + 4) * (kResidentSX + 4) +
-           ct * (kResidentSY + 2) * (kResidentSX + 2) + 8;
+    return elem_bytes(storage) * (9 * (kResidentSY + 4) * (kResidentSX + 4) + 64) +
+           ct * (kResidentSY + 2) * (kResidentSX + 2) + 16;
 }
 
 int resident_tiles(const prc_params &p)

@@ -135,16 +135,39 @@ __device__ __forceinline__ void reflect(const Coef<CT> &c, ST (*P)[SY + 4][SX + 
     }
 }
 
-// Whether some population streams to grid node (x, y) from beyond a wall
-// (x or y next to a side that does not wrap): only such nodes have ghost
-// slots to fill.
+// The populations that stream to grid node (x, y) from beyond a wall (x or
+// y next to a side that does not wrap): bit a set when (x, y) - e_a lies
+// beyond one.  Only nodes with some bit set have ghost slots to fill.
 template <int BC>
-__device__ __forceinline__ bool beside_wall(int nx, int ny, int x, int y)
+__device__ __forceinline__ uint32_t wall_dirs(int nx, int ny, int x, int y)
 {
-    bool w = false;
-    if (!Bc<BC>::wrap_x) w |= (x == 0) | (x == nx - 1);
-    if (!Bc<BC>::wrap_y) w |= (y == 0) | (y == ny - 1);
-    return w;
+    uint32_t m = 0;
+#pragma unroll
+    for (int a = 1; a < 9; ++a) {
+        const int sx = x - EX[a], sy = y - EY[a];
+        bool out = false;
+        if (!Bc<BC>::wrap_x) out |= (sx < 0) | (sx >= nx);
+        if (!Bc<BC>::wrap_y) out |= (sy < 0) | (sy >= ny);
+        m |= out ? 1u << a : 0u;
+    }
+    return m;
+}
+
+// The ghost slots of slot (i, j) whose directions beyond a wall are `dirs`
+// (wall_dirs), as reflect above, without branches: a direction not in dirs
+// writes its value into `dump` instead, a slot of the lane's own that nothing
+// reads.  dirs is tested here, in the time loop, not kept as lane masks
+// across it.
+template <typename ST, int SX, int SY>
+__device__ __forceinline__ void reflect_dirs(ST (*P)[SY + 4][SX + 4], ST *dump, int i, int j,
+                                             uint32_t dirs, const ST *v)
+{
+    asm volatile("" : "+v"(dirs));
+#pragma unroll
+    for (int a = 1; a < 9; ++a) {
+        ST *dst = ((dirs >> a) & 1u) ? &P[a][j - EY[a] + 2][i - EX[a] + 2] : dump;
+        *dst = v[OPP[a]];
+    }
 }
 
 // One subdomain per workgroup, two nodes per thread.  Each thread owns one
@@ -181,6 +204,7 @@ __global__ void __launch_bounds__(kResidentThreads)
     static_assert(NI + NE == 2 * T && LI >= 0 && HALO <= T, "subdomain shape");
     __shared__ ST P[9][H2][W2];        // post-collision state, origin (2, 2)
     __shared__ CT D[SY + 2][SX + 2];   // densities, origin (1, 1)
+    __shared__ ST dump[64];           // writes of reflect_dirs that go nowhere
     __shared__ uint64_t s_base;
     __shared__ uint32_t s_abort, s_last;
 
@@ -238,7 +262,8 @@ __global__ void __launch_bounds__(kResidentThreads)
     // wall), that node's row (lid), and whether its sources are all the
     // subdomain's own
     int si[2], sj[2], hx[2], hy[2], ly[2];
-    bool act[2], own[2], wall[2];
+    bool act[2], own[2];
+    uint32_t wdir[2];  // wall_dirs of each node (0 beside no wall, or not in the grid)
     si[0] = 2 + t % IW;
     sj[0] = 2 + t / IW;
     if (t < L0 + LI) {  // inner nodes T .. NI - 1
@@ -254,7 +279,7 @@ __global__ void __launch_bounds__(kResidentThreads)
         ly[m] = y;
         act[m] = x0 + si[m] < c.nx && y0 + sj[m] < c.ny;
         own[m] = hx[m] >= 1 && hx[m] <= SX - 2 && hy[m] >= 1 && hy[m] <= SY - 2;
-        wall[m] = act[m] && beside_wall<BC>(c.nx, c.ny, x0 + si[m], y0 + sj[m]);
+        wdir[m] = act[m] ? wall_dirs<BC>(c.nx, c.ny, x0 + si[m], y0 + sj[m]) : 0u;
     }
     // the ring slot of this thread (threads below 2 (SX + 2) + 2 SY)
     const TileGeom<SX, SY> g(t);
@@ -283,21 +308,21 @@ __global__ void __launch_bounds__(kResidentThreads)
         }
     }
     const bool qring1 = qv && qi >= -1 && qi <= SX && qj >= -1 && qj <= SY;
-    const bool qwall = qring1 && beside_wall<BC>(c.nx, c.ny, x0 + qi, y0 + qj);
+    const uint32_t qdir = qring1 ? wall_dirs<BC>(c.nx, c.ny, x0 + qi, y0 + qj) : 0u;
 
     // ghost slots of the input state: every in-grid slot that streaming reads
     // from (own nodes, ring slots) reflects into the walls
     if (!inner) {
 #pragma unroll
         for (int m = 0; m < 2; ++m) {
-            if (wall[m]) {
+            if (wdir[m] != 0) {
                 ST v[9];
 #pragma unroll
                 for (int a = 0; a < 9; ++a) v[a] = P[a][sj[m] + 2][si[m] + 2];
                 reflect<ST, BC, SX, SY>(c, P, x0, y0, si[m], sj[m], v);
             }
         }
-        if (g.ring && in_grid(g.hx, g.hy) && beside_wall<BC>(c.nx, c.ny, x0 + g.hx, y0 + g.hy)) {
+        if (g.ring && in_grid(g.hx, g.hy) && wall_dirs<BC>(c.nx, c.ny, x0 + g.hx, y0 + g.hy) != 0) {
             ST v[9];
 #pragma unroll
             for (int a = 0; a < 9; ++a) v[a] = P[a][g.hy + 2][g.hx + 2];
@@ -379,7 +404,7 @@ __global__ void __launch_bounds__(kResidentThreads)
             for (int a = 0; a < 9; ++a) v[a] = bits_value<ST>(h[a].x);
 #pragma unroll
             for (int a = 0; a < 9; ++a) P[a][qj + 2][qi + 2] = v[a];
-            if (!inner && qwall) reflect<ST, BC, SX, SY>(c, P, x0, y0, qi, qj, v);
+            if (!inner && qdir != 0) reflect_dirs<ST, SX, SY>(P, &dump[t % 64], qi, qj, qdir, v);
         }
         __syncthreads();
         if (s_abort != 0) break;
@@ -417,7 +442,7 @@ __global__ void __launch_bounds__(kResidentThreads)
             }
 #pragma unroll
             for (int a = 0; a < 9; ++a) P[a][j + 2][i + 2] = v[a];
-            if (!inner && wall[m]) reflect<ST, BC, SX, SY>(c, P, x0, y0, i, j, v);
+            if (!inner && wdir[m] != 0) reflect_dirs<ST, SX, SY>(P, &dump[t % 64], i, j, wdir[m], v);
         };
         auto put_node = [&](int m) {
             ST v[9];
