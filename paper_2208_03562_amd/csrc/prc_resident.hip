@@ -63,8 +63,9 @@ prc_status current_device(ResidentDevice **out)
 size_t resident_lds_bytes(int storage)
 {
     const size_t ct = storage == PRC_F64 ? 8 : 4;
-    return elem_bytes(storage) * (9 * (kResidentSY + 4) * (kResidentSX + 4) + 64) +
-           ct * (kResidentSY + 2) * (kResidentSX + 2) + 16;
+    const size_t row = storage == PRC_F32 ? kResidentRowP<float> : kResidentRowP<uint16_t>;
+    return elem_bytes(storage) * (9 * (kResidentSY + 4) * row + 64) +
+           ct * (kResidentSY + 2) * kResidentRowD + 16;
 }
 
 int resident_tiles(const prc_params &p)

@@ -53,6 +53,12 @@ constexpr int kXchBot = 0, kXchTop = 9 * kXchRowPlane, kXchLeft = 18 * kXchRowPl
               kXchRight = kXchLeft + 9 * kXchColPlane;
 constexpr int kXchElems = kXchRight + 9 * kXchColPlane;
 constexpr uint32_t kXchPair = 8;  // bytes per exchanged value
+// Row lengths of the LDS state (elements) and density (words) arrays: 32
+// banks of 4 bytes, the inner nodes in rows of SX - 4 = 60; a row length of
+// 60 + 32 k words (FP32 state, densities) or 60 + 64 k elements (16-bit
+// state) puts consecutive inner nodes on consecutive banks
+template <typename ST> constexpr int kResidentRowP = sizeof(ST) == 4 ? 92 : 124;
+constexpr int kResidentRowD = 92;
 // cache policy of the exchanged values: agent scope (sc1)
 constexpr int kAgent = 16;
 
@@ -121,8 +127,8 @@ __device__ __forceinline__ void edge_pos(int k, int &i, int &j)
 // along opp(a).  Each ghost value has exactly one such slot, and the pull out
 // of LDS then needs no boundary test (the lid term is added afterwards, as in
 // pull_checked).
-template <typename ST, int BC, int SX, int SY, typename CT>
-__device__ __forceinline__ void reflect(const Coef<CT> &c, ST (*P)[SY + 4][SX + 4], int x0, int y0,
+template <typename ST, int BC, int SX, int SY, int PW, typename CT>
+__device__ __forceinline__ void reflect(const Coef<CT> &c, ST (*P)[SY + 4][PW], int x0, int y0,
                                         int i, int j, const ST *v)
 {
 #pragma unroll
@@ -158,8 +164,8 @@ __device__ __forceinline__ uint32_t wall_dirs(int nx, int ny, int x, int y)
 // writes its value into `dump` instead, a slot of the lane's own that nothing
 // reads.  dirs is tested here, in the time loop, not kept as lane masks
 // across it.
-template <typename ST, int SX, int SY>
-__device__ __forceinline__ void reflect_dirs(ST (*P)[SY + 4][SX + 4], ST *dump, int i, int j,
+template <typename ST, int SX, int SY, int PW>
+__device__ __forceinline__ void reflect_dirs(ST (*P)[SY + 4][PW], ST *dump, int i, int j,
                                              uint32_t dirs, const ST *v)
 {
     asm volatile("" : "+v"(dirs));
@@ -194,6 +200,10 @@ __global__ void __launch_bounds__(kResidentThreads)
     using CT = typename Mem<ST>::CT;
     constexpr int SX = kResidentSX, SY = kResidentSY, T = kResidentThreads;
     constexpr int W2 = SX + 4, H2 = SY + 4, N2 = W2 * H2;
+    // row lengths of the LDS arrays: consecutive inner nodes (rows of IW)
+    // fall on consecutive LDS banks across a row's end as well (PW - IW + 1
+    // elements, DW - IW + 1 words, apart: one bank)
+    constexpr int PW = kResidentRowP<ST>, DW = kResidentRowD;
     constexpr int HALO = 4 * W2 + 4 * SY;
     constexpr int FILL = (N2 + T - 1) / T;
     constexpr int IW = SX - 4, NI = (SX - 4) * (SY - 4);  // nodes two or more from the boundary
@@ -202,8 +212,8 @@ __global__ void __launch_bounds__(kResidentThreads)
     constexpr int LI = T - L0 - NE;                        // late inner nodes
     constexpr uint32_t E = sizeof(ST);
     static_assert(NI + NE == 2 * T && LI >= 0 && HALO <= T, "subdomain shape");
-    __shared__ ST P[9][H2][W2];        // post-collision state, origin (2, 2)
-    __shared__ CT D[SY + 2][SX + 2];   // densities, origin (1, 1)
+    __shared__ ST P[9][H2][PW];        // post-collision state, origin (2, 2)
+    __shared__ CT D[SY + 2][DW];       // densities, origin (1, 1)
     __shared__ ST dump[64];           // writes of reflect_dirs that go nowhere
     __shared__ uint64_t s_base;
     __shared__ uint32_t s_abort, s_last;
@@ -319,21 +329,21 @@ __global__ void __launch_bounds__(kResidentThreads)
                 ST v[9];
 #pragma unroll
                 for (int a = 0; a < 9; ++a) v[a] = P[a][sj[m] + 2][si[m] + 2];
-                reflect<ST, BC, SX, SY>(c, P, x0, y0, si[m], sj[m], v);
+                reflect<ST, BC, SX, SY, PW>(c, P, x0, y0, si[m], sj[m], v);
             }
         }
         if (g.ring && in_grid(g.hx, g.hy) && wall_dirs<BC>(c.nx, c.ny, x0 + g.hx, y0 + g.hy) != 0) {
             ST v[9];
 #pragma unroll
             for (int a = 0; a < 9; ++a) v[a] = P[a][g.hy + 2][g.hx + 2];
-            reflect<ST, BC, SX, SY>(c, P, x0, y0, g.hx, g.hy, v);
+            reflect<ST, BC, SX, SY, PW>(c, P, x0, y0, g.hx, g.hy, v);
         }
         __syncthreads();
     }
 
     const rsrc_t rx = make_rsrc(xch, (uint32_t)(2 * ntiles * kXchElems) * kXchPair);
     auto pull = [&](int hi, int hj, int y, CT d[9]) {
-        pull_lds_inner<ST, SX, SY>(P, hi, hj, d);
+        pull_lds_inner<ST, SX, SY, PW>(P, hi, hj, d);
         if (!inner) add_lid<BC>(c, y, d);
     };
     auto collide_at = [&](int i, int j, CT d[9]) {
@@ -404,7 +414,7 @@ __global__ void __launch_bounds__(kResidentThreads)
             for (int a = 0; a < 9; ++a) v[a] = bits_value<ST>(h[a].x);
 #pragma unroll
             for (int a = 0; a < 9; ++a) P[a][qj + 2][qi + 2] = v[a];
-            if (!inner && qdir != 0) reflect_dirs<ST, SX, SY>(P, &dump[t % 64], qi, qj, qdir, v);
+            if (!inner && qdir != 0) reflect_dirs<ST, SX, SY, PW>(P, &dump[t % 64], qi, qj, qdir, v);
         }
         __syncthreads();
         if (s_abort != 0) break;
@@ -442,7 +452,7 @@ __global__ void __launch_bounds__(kResidentThreads)
             }
 #pragma unroll
             for (int a = 0; a < 9; ++a) P[a][j + 2][i + 2] = v[a];
-            if (!inner && wdir[m] != 0) reflect_dirs<ST, SX, SY>(P, &dump[t % 64], i, j, wdir[m], v);
+            if (!inner && wdir[m] != 0) reflect_dirs<ST, SX, SY, PW>(P, &dump[t % 64], i, j, wdir[m], v);
         };
         auto put_node = [&](int m) {
             ST v[9];

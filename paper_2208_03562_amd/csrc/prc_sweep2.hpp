@@ -99,9 +99,10 @@ __device__ __forceinline__ void pull_lds(const Coef<typename Mem<ST>::CT> &c,
     }
 }
 
-// The same for a slot whose sources all lie inside the grid.
-template <typename ST, int TX, int TY>
-__device__ __forceinline__ void pull_lds_inner(const ST (*P)[TY + 4][TX + 4], int hi, int hj,
+// The same for a slot whose sources all lie inside the grid (PW: the row
+// length of the LDS array, TX + 4 or more).
+template <typename ST, int TX, int TY, int PW = TX + 4>
+__device__ __forceinline__ void pull_lds_inner(const ST (*P)[TY + 4][PW], int hi, int hj,
                                                typename Mem<ST>::CT d[9])
 {
 #pragma unroll
