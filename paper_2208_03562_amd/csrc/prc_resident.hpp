@@ -237,10 +237,11 @@ __global__ void __launch_bounds__(kResidentThreads)
         s_base = ld_agent(&sy->step);
         s_abort = 0;
     }
+    // (the loads first; this thread's set-up below overlaps their latency)
+    CT v[FILL][9];
+    bool ok[FILL];
     {
         const rsrc_t rs = make_rsrc(buf0, c.state_bytes);
-        CT v[FILL][9];
-        bool ok[FILL];
         uint32_t o[FILL];
 #pragma unroll
         for (int m = 0; m < FILL; ++m) {
@@ -255,17 +256,7 @@ __global__ void __launch_bounds__(kResidentThreads)
                 for (int a = 0; a < 9; ++a) v[m][a] = Mem<ST>::ld(rs, o[m], a * c.plane_bytes);
             }
         }
-#pragma unroll
-        for (int m = 0; m < FILL; ++m) {
-            const int k = t + m * T;
-            if (ok[m]) {
-#pragma unroll
-                for (int a = 0; a < 9; ++a) P[a][k / W2][k % W2] = LdsVal<ST>::put(v[m][a]);
-            }
-        }
     }
-    __syncthreads();
-    const uint64_t base = s_base;
 
     // this thread's two nodes (si, sj), whether each is in the grid, the
     // slot its streaming reads around (the clamped node for a node beyond a
@@ -319,6 +310,20 @@ __global__ void __launch_bounds__(kResidentThreads)
     }
     const bool qring1 = qv && qi >= -1 && qi <= SX && qj >= -1 && qj <= SY;
     const uint32_t qdir = qring1 ? wall_dirs<BC>(c.nx, c.ny, x0 + qi, y0 + qj) : 0u;
+
+    // the loaded state into LDS
+    {
+#pragma unroll
+        for (int m = 0; m < FILL; ++m) {
+            const int k = t + m * T;
+            if (ok[m]) {
+#pragma unroll
+                for (int a = 0; a < 9; ++a) P[a][k / W2][k % W2] = LdsVal<ST>::put(v[m][a]);
+            }
+        }
+    }
+    __syncthreads();
+    const uint64_t base = s_base;
 
     // ghost slots of the input state: every in-grid slot that streaming reads
     // from (own nodes, ring slots) reflects into the walls
