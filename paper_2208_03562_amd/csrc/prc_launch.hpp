@@ -73,10 +73,11 @@ prc_status launch_sweep_wide(const prc_params &p, int tile, const void *src, voi
 prc_status resident_prepare(hipStream_t s);
 // (capturing: whether s is under graph capture, -1 to ask the runtime;
 // start/stop, if given, are recorded by the dispatch of the first and the
-// last kernel: the start of the first, the end of the last)
+// last kernel: the start of the first, the end of the last; after, if given,
+// is recorded on s behind the last kernel)
 prc_status launch_resident(const prc_params &p, const void *src, void *dst, int64_t nsteps,
                            hipStream_t s, int capturing = -1, hipEvent_t start = nullptr,
-                           hipEvent_t stop = nullptr);
+                           hipEvent_t stop = nullptr, hipEvent_t after = nullptr);
 prc_status resident_report();
 prc_status resident_release();
 // wait limit of later resident launches, in 100 MHz ticks (-1: the default)

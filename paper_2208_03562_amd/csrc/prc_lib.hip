@@ -202,11 +202,12 @@ static int single_step_tile(int tile)
 // buffer the single-step sequence puts it in; single steps do the rest.
 static prc_status run_steps(const prc_params &p, int tile, void *f_a, void *f_b, int64_t k0,
                             int64_t n, hipStream_t s, int capturing = -1,
-                            hipEvent_t start = nullptr, hipEvent_t stop = nullptr)
+                            hipEvent_t start = nullptr, hipEvent_t stop = nullptr,
+                            hipEvent_t after = nullptr)
 {
     if (tile == kResidentTile)  // any number of steps per launch
         return launch_resident(p, (k0 & 1) ? f_b : f_a, (k0 & 1) ? f_a : f_b, n, s, capturing,
-                               start, stop);
+                               start, stop, after);
     prc_status st = PRC_OK;
     int64_t k = k0;
     const int64_t end = k0 + n;
@@ -535,11 +536,12 @@ prc_status prc_init(const prc_params *p, void *f, hipStream_t stream)
 }
 
 static prc_status step_impl(const prc_params *p, void *f_a, void *f_b, int64_t nsteps,
-                            hipEvent_t start, hipEvent_t stop, hipStream_t stream);
+                            hipEvent_t start, hipEvent_t stop, bool kernel_only,
+                            hipStream_t stream);
 
 prc_status prc_step(const prc_params *p, void *f_a, void *f_b, int64_t nsteps, hipStream_t stream)
 {
-    return step_impl(p, f_a, f_b, nsteps, nullptr, nullptr, stream);
+    return step_impl(p, f_a, f_b, nsteps, nullptr, nullptr, false, stream);
 }
 
 prc_status prc_step_timed(const prc_params *p, void *f_a, void *f_b, int64_t nsteps,
@@ -547,15 +549,12 @@ prc_status prc_step_timed(const prc_params *p, void *f_a, void *f_b, int64_t nst
                           hipStream_t stream)
 {
     if (!start || !stop) return fail(PRC_EINVAL, "NULL start or stop event");
-    if (kernel_only) return step_impl(p, f_a, f_b, nsteps, start, stop, stream);
-    HIP_TRY(hipEventRecord(start, stream));
-    const prc_status st = step_impl(p, f_a, f_b, nsteps, nullptr, nullptr, stream);
-    if (st == PRC_OK) HIP_TRY(hipEventRecord(stop, stream));
-    return st;
+    return step_impl(p, f_a, f_b, nsteps, start, stop, kernel_only != 0, stream);
 }
 
 static prc_status step_impl(const prc_params *p, void *f_a, void *f_b, int64_t nsteps,
-                            hipEvent_t start, hipEvent_t stop, hipStream_t stream)
+                            hipEvent_t start, hipEvent_t stop, bool kernel_only,
+                            hipStream_t stream)
 {
     prc_status st = validate(p);
     if (st != PRC_OK) return st;
@@ -576,10 +575,15 @@ static prc_status step_impl(const prc_params *p, void *f_a, void *f_b, int64_t n
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     HIP_TRY(hipStreamIsCapturing(stream, &cap));
     const int capturing = cap == hipStreamCaptureStatusNone ? 0 : 1;
-    // timed calls: the resident sweep's dispatch records the events itself
-    // (the kernel's own start and end); other shapes bracket the call
-    if (tile == kResidentTile && nsteps > 0)
-        return run_steps(*p, tile, f_a, f_b, 0, nsteps, stream, capturing, start, stop);
+    // timed calls: the events bracket the call's work on the stream; for the
+    // resident sweep with kernel_only its dispatch records them (the
+    // kernel's own start and end), otherwise its launch records the stop
+    // event ahead of its own ordering event
+    if (tile == kResidentTile && nsteps > 0) {
+        if (kernel_only) return run_steps(*p, tile, f_a, f_b, 0, nsteps, stream, capturing, start, stop);
+        if (start) HIP_TRY(hipEventRecord(start, stream));
+        return run_steps(*p, tile, f_a, f_b, 0, nsteps, stream, capturing, nullptr, nullptr, stop);
+    }
     if (start) HIP_TRY(hipEventRecord(start, stream));
     // (the resident sweep takes any number of steps in one launch: no graph)
     if (tile != kResidentTile && gsteps > 0 && !capturing && nsteps >= 2 * gsteps) {

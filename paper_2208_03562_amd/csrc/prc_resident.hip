@@ -153,7 +153,8 @@ prc_status resident_prepare(hipStream_t s)
 }
 
 prc_status launch_resident(const prc_params &p, const void *src, void *dst, int64_t nsteps,
-                           hipStream_t s, int capturing, hipEvent_t start, hipEvent_t stop)
+                           hipStream_t s, int capturing, hipEvent_t start, hipEvent_t stop,
+                           hipEvent_t after)
 {
     ResidentDevice *d = nullptr;
     prc_status st = current_device(&d);
@@ -184,6 +185,9 @@ prc_status launch_resident(const prc_params &p, const void *src, void *dst, int6
         if (n & 1) std::swap(a, b);  // an odd count leaves the state in the second buffer
         nsteps -= n;
     }
+    // the caller's event first: the ordering event's marker would otherwise
+    // lie inside the caller's interval
+    if (after && st == PRC_OK) HIP_TRY(hipEventRecord(after, s));
     if (track && st == PRC_OK) {
         HIP_TRY(hipEventRecord(d->last, s));
         d->has_last = true;
