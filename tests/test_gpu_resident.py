@@ -209,3 +209,32 @@ def test_timed_step_gives_the_same_bits_and_a_kernel_time(tile):
     assert bool((sol.get_state() == ref).all())
     capi.prc_set_tile(sol.p, -1)
     capi.prc_release_graphs()
+
+
+def draw_resident(seed):
+    """A seeded random problem the resident sweep takes: up to 16 x 16
+    subdomains (grids up to 1024 x 512, ragged on walled sides, whole
+    subdomains on periodic ones), any boundary type, 32- or 16-bit storage,
+    the method as published or a general setting, 1 to 29 steps."""
+    import numpy as np
+    rng = np.random.default_rng(5000 + seed)
+    bc = ["cavity", "periodic", "channel"][rng.integers(3)]
+    nx = int(rng.integers(3, 1025)) if bc == "cavity" else 64 * int(rng.integers(1, 17))
+    ny = 32 * int(rng.integers(1, 17)) if bc == "periodic" else int(rng.integers(3, 513))
+    r = float(rng.choice([0.5, 1.0, 2.0]))
+    extra = dict(u_lid=0.0 if bc == "periodic" else float(rng.uniform(0.0, 0.05)))
+    if rng.random() < 0.5:
+        extra.update(corrections=int(rng.integers(0, 8)), frame=int(rng.integers(2)),
+                     omega_xi=float(rng.uniform(0.8, 1.5)), omega_3=float(rng.uniform(0.8, 1.5)),
+                     fx=float(rng.uniform(-1e-5, 1e-5)), fy=float(rng.uniform(-1e-5, 1e-5)))
+    s = spec(nx, ny, r, float(rng.uniform(0.1, 1.0)), omega_nu=float(rng.uniform(0.6, 1.8)), bc=bc,
+             storage=["f32", "f16", "bf16"][rng.integers(3)], **extra)
+    return s, int(rng.integers(1, 30))
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_resident_random_problem_gives_the_single_step_bits(seed):
+    s, nsteps = draw_resident(seed)
+    ref = run(s, 0, nsteps, seed=seed)
+    got = run(s, RESIDENT, nsteps, seed=seed)
+    assert bool((got == ref).all()), (s, nsteps)
