@@ -201,8 +201,9 @@ __global__ void __launch_bounds__(kResidentThreads)
     constexpr int SX = kResidentSX, SY = kResidentSY, T = kResidentThreads;
     constexpr int W2 = SX + 4, H2 = SY + 4, N2 = W2 * H2;
     // row lengths of the LDS arrays: consecutive inner nodes (rows of IW)
-    // fall on consecutive LDS banks across a row's end as well (PW - IW + 1
-    // elements, DW - IW + 1 words, apart: one bank)
+    // stay on consecutive LDS banks across a row's end, where their slots
+    // lie PW - IW + 1 elements (DW - IW + 1 words) apart, one element more
+    // than a whole number of 128-byte bank rounds
     constexpr int PW = kResidentRowP<ST>, DW = kResidentRowD;
     constexpr int HALO = 4 * W2 + 4 * SY;
     constexpr int FILL = (N2 + T - 1) / T;
