@@ -56,6 +56,8 @@ struct Coef {
     CT sPQ, dPQ;            // (P_gamma + Q_gamma)/4, (P_gamma - Q_gamma)/4
     CT sa0, sb0, sc0, se0;  // constant parts of the strain system for Dx +- Dy
     CT c4hnu;               // 4 c2 h_nu
+    CT c2hnu2;              // 2 c2 h_nu (half of c4hnu)
+    CT okq11, okl11;        // omega_nu kq11, omega_nu kl11
     CT om_nu, om_xi, om_3, om_4;
     CT fxh, fyh;            // F / (2 gamma) (eq. hydrodynamicfields)
     CT fxg, fyg;            // F / gamma: change of the first-order central moments
@@ -138,6 +140,9 @@ inline Coef<CT> make_coef(const prc_params &p, int64_t row_stride, int64_t plane
         c.se0 = CT(0.5 * (sx0 - sy0));
     }
     c.c4hnu = CT(4.0 * c2 * hnu);
+    c.c2hnu2 = CT(2.0 * c2 * hnu);
+    c.okq11 = CT(p.omega_nu * -Qg * hnu);
+    c.okl11 = CT(p.omega_nu * -(1.0 / g - 1.0) * hnu * c2);
     c.om_nu = CT(p.omega_nu);
     c.om_xi = CT(p.omega_xi);
     c.om_3 = CT(p.omega_3);

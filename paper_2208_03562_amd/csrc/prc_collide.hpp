@@ -233,13 +233,17 @@ __device__ __forceinline__ void collide(const Coef<CT> &c, CT d[9], CT gx, CT gy
 //   k2d: -2 h_nu (n2d + (2 c2 / omega_nu) (Dx - Dy)),
 // so that relaxing with omega_xi = 1 and omega_nu gives the changes
 //   d2s = -2 n2s - 2 c2 (Dx + Dy),  d2d = -2 n2d - 4 c2 h_nu (Dx - Dy)
-// (the same terms as in corrections(), summed in closed form).  Only
-// Ds = Dx + Dy and Dm = Dx - Dy are needed, so the system is solved for them:
-// its coefficients are linear in ux^2 + uy^2 and ux^2 - uy^2.
+// (the same terms as in corrections(), summed in closed form), returned here
+// as their halves h2s = d2s / 2, h2d = d2d / 2 (the changes of k20 and k02
+// are their sum and difference).  Only Ds = Dx + Dy and Dm = Dx - Dy are
+// needed, so the system is solved for them: its coefficients are linear in
+// ux^2 + uy^2 and ux^2 - uy^2.  Products are grouped so that each multiply
+// fuses with an add (fewer instructions; the rounding differs from the
+// term-by-term sum, within FP32 rounding).
 template <typename CT>
 __device__ __forceinline__ void increments_plain(const Coef<CT> &c, CT ux, CT uy, CT u2s, CT u2d,
                                                  CT uxy, CT n2s, CT n2d, CT n11, CT gx, CT gy,
-                                                 CT &d2s, CT &d2d, CT &d11)
+                                                 CT &h2s, CT &h2d, CT &d11)
 {
     // a Ds + b Dm = R2s, cc Ds + e Dm = R2d with a = (cbx + cby)/2,
     // b = (cbx - cby)/2, cc = (csx + csy)/2, e = (csx - csy)/2, where
@@ -249,16 +253,17 @@ __device__ __forceinline__ void increments_plain(const Coef<CT> &c, CT ux, CT uy
     const CT b = c.dPQ * u2d + c.sb0;
     const CT cc = c.sPQ * u2d + c.sc0;
     const CT e = c.dPQ * u2s + c.se0;
-    const CT Agx = c.Ab * ux * gx, Bgy = c.Bb * uy * gy;  // -e_b = Agx + Bgy
-    const CT R2s = n2s - (Agx + Bgy);
-    const CT R2d = n2d + (Bgy - Agx);
+    // -e_b = Ab ux gx + Bb uy gy, -e_s = Ab ux gx - Bb uy gy
+    const CT tA = c.Ab * ux, tB = c.Bb * uy;
+    const CT R2s = n2s - tA * gx - tB * gy;
+    const CT R2d = n2d - tA * gx + tB * gy;
     const CT idet = recip(a * e - b * cc);
     const CT Ds = (R2s * e - b * R2d) * idet;
     const CT Dm = (a * R2d - cc * R2s) * idet;
-    d2s = CT(-2) * n2s - c.c2x2 * Ds;
-    d2d = CT(-2) * n2d - c.c4hnu * Dm;
-    const CT cor11 = c.kq11 * uxy * Ds + c.kl11 * (uy * gx + ux * gy);
-    d11 = c.om_nu * (cor11 - n11);
+    h2s = -c.c2 * Ds - n2s;
+    h2d = -c.c2hnu2 * Dm - n2d;
+    // omega_nu (cor11 - n11), cor11 = kq11 uxy Ds + kl11 (uy gx + ux gy)
+    d11 = c.okq11 * uxy * Ds + c.okl11 * (uy * gx + ux * gy) - c.om_nu * n11;
 }
 
 // The method as the paper runs it (every correction, unit rates for the
@@ -303,28 +308,29 @@ __device__ __forceinline__ void collide_plain(const Coef<CT> &c, CT d[9], CT gx,
     const CT k2s = k20 + k02;  // minus 2 c2 rho0
     const CT k2d = k20 - k02;
 
-    // preconditioned equilibria (eq. 14), minus the same constants
+    // non-equilibrium parts: minus the preconditioned equilibria (eq. 14),
+    // e2s = 2 c2 drho + (1/gamma - 1) rho (ux^2 + uy^2) (minus the same
+    // constants), e2d = (1/gamma - 1) rho (ux^2 - uy^2), e11 likewise
     const CT u2d = ux2 - uy2;
     const CT irh = c.ig1 * rho;
-    const CT e2s = c.c2x2 * drho + irh * u2s;
-    const CT e2d = irh * u2d;
-    const CT e11 = irh * uxy;
+    const CT n2s = k2s - c.c2x2 * drho - irh * u2s;
+    const CT n2d = k2d - irh * u2d;
+    const CT n11 = k11 - irh * uxy;
 
     // changes of the second central moments in the collision, the same as
     // those of the raw second moments
-    CT d2s, d2d, d11;
-    increments_plain(c, ux, uy, u2s, u2d, uxy, k2s - e2s, k2d - e2d, k11 - e11, gx, gy, d2s, d2d,
-                     d11);
-    const CT d20 = CT(0.5) * (d2s + d2d), d02 = CT(0.5) * (d2s - d2d);
+    CT h2s, h2d, d11;
+    increments_plain(c, ux, uy, u2s, u2d, uxy, n2s, n2d, n11, gx, gy, h2s, h2d, d11);
+    const CT d20 = h2s + h2d, d02 = h2s - h2d;
 
     // raw third and fourth moments after the collision from the central ones
     // (k21 = g3 rho ux^2 uy, k12 = g3 rho ux uy^2, k22 = c2^2 rho), minus the
     // raw moments before it (those of rho0 w: 0, 0, rho0 c2^2)
     const CT A = (k20 + d20) + c.c2rho0, B = (k02 + d02) + c.c2rho0;  // k20, k02 of f
-    const CT K11 = k11 + d11;
+    const CT K11 = k11 + d11, K2 = K11 + K11;
     const CT rg = c.g3p1 * rho;  // (g3 + 1) rho
-    const CT d21 = (uy * (rg * ux2 + A) + (ux + ux) * K11) - c.r * (X2[2] - X2[0]);
-    const CT d12 = (ux * (rg * uy2 + B) + (uy + uy) * K11) - c.r2 * (X1[2] + X1[0]);
+    const CT d21 = (uy * (rg * ux2 + A) + ux * K2) - c.r * (X2[2] - X2[0]);
+    const CT d12 = (ux * (rg * uy2 + B) + uy * K2) - c.r2 * (X1[2] + X1[0]);
     const CT d22 = (((c.c2sq * drho + (c.g34p1 * rho) * (ux2 * uy2)) + (ux2 * B + uy2 * A)) +
                     CT(4) * uxy * K11) -
                    c.r2 * (X2[2] + X2[0]);
