@@ -337,32 +337,26 @@ __device__ __forceinline__ void collide_plain(const Coef<CT> &c, CT d[9], CT gx,
 
     // f~ = f + P^-1 S^-1 dm (dm00 = dm10 = dm01 = 0): y-transform back for
     // each x-moment, halved (the halves of the x-transform folded in) ...
-    CT G[3][3];  // [x-moment][e_y + 1]
-    {
-        const CT b = c.qinv_r2 * d02;
-        G[0][0] = b;
-        G[0][1] = CT(-2) * b;
-        G[0][2] = b;
-    }
-    {
-        const CT a = c.qinv_r * d11, b = c.qinv_r2 * d12;
-        G[1][0] = b - a;
-        G[1][1] = CT(-2) * b;
-        G[1][2] = b + a;
-    }
-    {
-        const CT a = c.qinv_r * d21, b = c.qinv_r2 * d22;
-        G[2][0] = b - a;
-        G[2][1] = CT(0.5) * d20 - CT(2) * b;
-        G[2][2] = b + a;
-    }
-    // ... then the x-transform back for each row, added to the populations
+    // G[m][e_y + 1] for x-moments m: (b0, -2 b0, b0), (b1 - a1, -2 b1, b1 + a1),
+    // (b2 - a2, d20 / 2 - 2 b2, b2 + a2)
+    const CT b0 = c.qinv_r2 * d02;
+    const CT a1 = c.qinv_r * d11, b1 = c.qinv_r2 * d12;
+    const CT a2 = c.qinv_r * d21, b2 = c.qinv_r2 * d22;
+    // ... then the x-transform back for each row (K0, K1, K2 = G[0..2][row]:
+    // changes K2 - K1, 2 (K0 - K2), K2 + K1), added to the populations; the
+    // middle row written out so that its factors of 2 fuse
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        const CT K0 = G[0][j], K1 = G[1][j], K2 = G[2][j];
+    for (int j = 0; j < 3; j += 2) {
+        const CT K1 = j == 0 ? b1 - a1 : b1 + a1, K2 = j == 0 ? b2 - a2 : b2 + a2;
         q[j][0] += K2 - K1;
-        q[j][1] += CT(2) * (K0 - K2);
+        q[j][1] += CT(2) * (b0 - K2);
         q[j][2] += K2 + K1;
+    }
+    {
+        const CT H = CT(0.5) * d20 - CT(2) * b2;  // K2 of the middle row; K0 = -2 b0, K1 = -2 b1
+        q[1][0] += CT(2) * b1 + H;
+        q[1][1] += CT(-2) * (CT(2) * b0 + H);
+        q[1][2] += CT(-2) * b1 + H;
     }
 #pragma unroll
     for (int a = 0; a < 9; ++a) d[a] = q[QJ[a]][QI[a]];
