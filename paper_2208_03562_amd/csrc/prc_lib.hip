@@ -146,20 +146,20 @@ static int tile_choice(const prc_params &p)
         if (it != g_tuned.end()) return it->second;
     }
     // measured on MI355X: a grid whose state fits the LDS of the chip with
-    // one subdomain per CU runs the resident sweep (1024 x 512 FP32: 5.0
+    // one subdomain per CU runs the resident sweep (1024 x 512 FP32: 3.6
     // against 6.2 us per step for two steps per launch); on other grids that
-    // fill the chip two steps per launch pay for every storage type.  FP32:
-    // 64 x 16 tiles while the two states stay in the last-level cache,
-    // 32 x 32 for states streamed from HBM; 16-bit: 64 x 16; FP64 (twice the
-    // LDS per tile, so 512-thread tiles): 64 x 8 in the cache, 32 x 16 from
-    // HBM
+    // fill the chip two steps per launch pay for every storage type.  FP32
+    // and 16-bit: 64 x 16 tiles (4096 x 2048 FP32: 71.5 against 73.1 us per
+    // step on 32 x 32); FP64 (twice the LDS per tile, so 512-thread tiles):
+    // 64 x 8 in the last-level cache, 32 x 16 from HBM
     if (p.nx >= 256 && p.ny >= 64) {
         if (resident_allowed(p)) return kResidentTile;
-        int64_t row, plane, total;
-        layout(p, row, plane, total);
-        const bool cached = 2 * total * (int64_t)elem_bytes(p.storage) <= kNtPairBytes;
-        if (p.storage == PRC_F64) return cached ? 5 : 6;
-        if (p.storage == PRC_F32) return cached ? 7 : 8;
+        if (p.storage == PRC_F64) {
+            int64_t row, plane, total;
+            layout(p, row, plane, total);
+            const bool cached = 2 * total * (int64_t)elem_bytes(p.storage) <= kNtPairBytes;
+            return cached ? 5 : 6;
+        }
         return 7;
     }
     return p.nx >= 256 ? 2 : 0;
