@@ -470,6 +470,10 @@ __global__ void __launch_bounds__(kResidentThreads)
             if (act[0]) put_node(0);
             if (act[1]) put_node(1);
         } else {
+            // the late waves are the phase's critical path: their
+            // instructions go first wherever the early waves' LDS writes
+            // compete with them (measured 1 % faster per step)
+            __builtin_amdgcn_s_setprio(3);
             if (act[1]) {
                 collide_at(si[1], sj[1], d[1]);
                 const int i = si[1], j = sj[1];
@@ -498,6 +502,7 @@ __global__ void __launch_bounds__(kResidentThreads)
                 put(1, v);
             }
             if (act[0]) put_node(0);
+            __builtin_amdgcn_s_setprio(0);
         }
         __syncthreads();
     }
