@@ -835,7 +835,8 @@ def main():
 
 STEADY_STEPS, STEADY_WARMUP = 12000, 2000
 ROOFLINE_NOTE = ("kernel_us: HIP events recorded on the solver's stream around the timed "
-                 "chunk by prc_step_timed (the resident sweep runs a chunk as one launch; other "
+                 "chunk by prc_step_timed (the resident sweep runs a chunk as one launch, start "
+                 "a marker before it, stop recorded by its dispatch at the kernel's end; other "
                  "shapes: the mean "
                  "over the chunk's launches); it includes the dispatch.  kernel_only_us: one "
                  "more call of the same length after the timed region, its events recorded by "

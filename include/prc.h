@@ -163,12 +163,13 @@ prc_status prc_step(const prc_params *p, void *f_a, void *f_b, int64_t nsteps,
 
 /* prc_step, timed: start and stop (events created by the caller, e.g. with
  * hipEventCreate; timing enabled) are recorded on `stream` before and after
- * the call's work.  With kernel_only set, the resident sweep's dispatch
- * records them itself (hipExtLaunchKernel): start when the first launch of
- * the call begins, stop when its last launch ends, so hipEventElapsedTime
- * gives kernel time alone (as a kernel trace reports it; such a launch takes
- * longer to dispatch); other shapes record them around the call either way.
- * PRC_EINVAL if either event is NULL. */
+ * the call's work; for the resident sweep stop is recorded by its last
+ * launch itself (hipExtLaunchKernel), when that kernel ends.  With
+ * kernel_only set, the resident sweep's dispatch records both: start when
+ * the first launch of the call begins, stop when its last launch ends, so
+ * hipEventElapsedTime gives kernel time alone (as a kernel trace reports it;
+ * such a launch takes longer to dispatch); other shapes record them around
+ * the call either way.  PRC_EINVAL if either event is NULL. */
 prc_status prc_step_timed(const prc_params *p, void *f_a, void *f_b, int64_t nsteps,
                           hipEvent_t start, hipEvent_t stop, int32_t kernel_only,
                           hipStream_t stream);

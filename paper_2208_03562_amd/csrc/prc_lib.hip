@@ -577,8 +577,9 @@ static prc_status step_impl(const prc_params *p, void *f_a, void *f_b, int64_t n
     const int capturing = cap == hipStreamCaptureStatusNone ? 0 : 1;
     // timed calls: the events bracket the call's work on the stream; for the
     // resident sweep with kernel_only its dispatch records them (the
-    // kernel's own start and end), otherwise its launch records the stop
-    // event ahead of its own ordering event
+    // kernel's own start and end), otherwise start is a marker ahead of the
+    // launch and the last dispatch records stop (ahead of the launch's own
+    // ordering event)
     if (tile == kResidentTile && nsteps > 0) {
         if (kernel_only) return run_steps(*p, tile, f_a, f_b, 0, nsteps, stream, capturing, start, stop);
         if (start) HIP_TRY(hipEventRecord(start, stream));

@@ -174,20 +174,23 @@ prc_status launch_resident(const prc_params &p, const void *src, void *dst, int6
     // (launches captured into a graph are ordered by whoever replays it)
     const bool track = cap == hipStreamCaptureStatusNone;
     if (track && d->has_last && d->last_stream != s) HIP_TRY(hipStreamWaitEvent(s, d->last, 0));
+    // The caller's event after the call is recorded by the last dispatch
+    // itself, at the kernel's end, and the ordering event by a marker after
+    // it: a marker right after a kernel adds no latency, but a second marker
+    // behind the caller's added about 4 us to the call.
+    hipEvent_t end = stop ? stop : after;
     void *a = const_cast<void *>(src), *b = dst;
     bool first = true;
     while (nsteps > 0 && st == PRC_OK) {
         const int64_t n = nsteps < kResidentMaxSteps ? nsteps : kResidentMaxSteps;
         const bool last = n == nsteps;
         st = PRC_DISPATCH(p, launch_res, p, a, b, (int)n, *d, s, first ? start : nullptr,
-                          last ? stop : nullptr);
+                          last ? end : nullptr);
         first = false;
         if (n & 1) std::swap(a, b);  // an odd count leaves the state in the second buffer
         nsteps -= n;
     }
-    // the caller's event first: the ordering event's marker would otherwise
-    // lie inside the caller's interval
-    if (after && st == PRC_OK) HIP_TRY(hipEventRecord(after, s));
+    if (stop && after && st == PRC_OK) HIP_TRY(hipEventRecord(after, s));
     if (track && st == PRC_OK) {
         HIP_TRY(hipEventRecord(d->last, s));
         d->has_last = true;

@@ -126,11 +126,15 @@ def test_resident_steps_captured_by_the_caller():
         capi.prc_release_graphs()
 
 
-def test_resident_calls_on_two_streams_give_the_single_step_bits():
+@pytest.mark.parametrize("mode", ["plain", "timed", "kernel_only"])
+def test_resident_calls_on_two_streams_give_the_single_step_bits(mode):
     """Two problems on two streams issue resident calls back to back with no
     synchronisation between them: the library orders resident launches on one
     device (a launch on another stream waits for the latest one), so each
-    problem gets the single-step bits and no launch loses a wait."""
+    problem gets the single-step bits and no launch loses a wait.  Plain
+    calls, timed calls (the caller's events around the call: the launch
+    records its ordering event itself) and timed calls whose dispatch records
+    the caller's events."""
     from paper_2208_03562_amd import capi, solver
     specs = [spec(200, 90, 2.0, 0.5, omega_nu=1.3, u_lid=0.05, storage="f32"),
              spec(256, 128, 0.5, 0.2, omega_nu=1.1, u_lid=0.02, storage="f32")]
@@ -143,10 +147,19 @@ def test_resident_calls_on_two_streams_give_the_single_step_bits():
         capi.prc_set_tile(sol.p, RESIDENT)
         sol.set_state(workloads.deviation_noise(s["nx"], s["ny"], 20 + k, 1e-3))
         sols.append(sol)
+    events = []
+    for k in range(2):
+        ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        ev[0].record(streams[k])
+        ev[1].record(streams[k])
+        events.append(ev)
     torch.cuda.synchronize()
     for i in range(4):
         for k in range(2):
-            sols[k].step(counts[k][i])
+            if mode == "plain":
+                sols[k].step(counts[k][i])
+            else:
+                sols[k].step_timed(counts[k][i], *events[k], kernel_only=(mode == "kernel_only"))
     torch.cuda.synchronize()
     capi.prc_resident_status()  # raises if a launch lost a wait
     for k in range(2):
