@@ -146,7 +146,7 @@ static int tile_choice(const prc_params &p)
         if (it != g_tuned.end()) return it->second;
     }
     // measured on MI355X: a grid whose state fits the LDS of the chip with
-    // one subdomain per CU runs the resident sweep (1024 x 512 FP32: 3.6
+    // one subdomain per CU runs the resident sweep (1024 x 512 FP32: 3.5
     // against 6.2 us per step for two steps per launch); on other grids that
     // fill the chip two steps per launch pay for every storage type.  FP32
     // and 16-bit: 64 x 16 tiles (4096 x 2048 FP32: 71.5 against 73.1 us per
