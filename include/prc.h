@@ -168,8 +168,9 @@ prc_status prc_step(const prc_params *p, void *f_a, void *f_b, int64_t nsteps,
  * kernel_only set, the resident sweep's dispatch records both: start when
  * the first launch of the call begins, stop when its last launch ends, so
  * hipEventElapsedTime gives kernel time alone (as a kernel trace reports it;
- * such a launch takes longer to dispatch); other shapes record them around
- * the call either way.  PRC_EINVAL if either event is NULL. */
+ * such a launch takes longer to dispatch); other shapes, and any call under
+ * graph capture, record them around the call either way.  PRC_EINVAL if
+ * either event is NULL. */
 prc_status prc_step_timed(const prc_params *p, void *f_a, void *f_b, int64_t nsteps,
                           hipEvent_t start, hipEvent_t stop, int32_t kernel_only,
                           hipStream_t stream);

@@ -75,7 +75,8 @@ prc_status resident_prepare(hipStream_t s);
 // start/stop, if given, are recorded by the dispatch of the first and the
 // last kernel: the start of the first, the end of the last; after, if given,
 // marks the end of the call's work: the last kernel's dispatch records it
-// when stop is not given, a marker behind it otherwise)
+// when stop is not given, a marker behind it otherwise; under capture all
+// three are markers around the launches)
 prc_status launch_resident(const prc_params &p, const void *src, void *dst, int64_t nsteps,
                            hipStream_t s, int capturing = -1, hipEvent_t start = nullptr,
                            hipEvent_t stop = nullptr, hipEvent_t after = nullptr);

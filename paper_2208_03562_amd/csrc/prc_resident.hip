@@ -177,20 +177,30 @@ prc_status launch_resident(const prc_params &p, const void *src, void *dst, int6
     // The caller's event after the call is recorded by the last dispatch
     // itself, at the kernel's end, and the ordering event by a marker after
     // it: a marker right after a kernel adds no latency, but a second marker
-    // behind the caller's added about 4 us to the call.
-    hipEvent_t end = stop ? stop : after;
+    // behind the caller's added about 4 us to the call.  Under graph capture
+    // every event is a marker (an event-record node) around plain launches.
+    hipEvent_t first_ev = start, end = stop ? stop : after;
+    if (!track) {
+        if (start) HIP_TRY(hipEventRecord(start, s));
+        first_ev = end = nullptr;
+    }
     void *a = const_cast<void *>(src), *b = dst;
     bool first = true;
     while (nsteps > 0 && st == PRC_OK) {
         const int64_t n = nsteps < kResidentMaxSteps ? nsteps : kResidentMaxSteps;
         const bool last = n == nsteps;
-        st = PRC_DISPATCH(p, launch_res, p, a, b, (int)n, *d, s, first ? start : nullptr,
+        st = PRC_DISPATCH(p, launch_res, p, a, b, (int)n, *d, s, first ? first_ev : nullptr,
                           last ? end : nullptr);
         first = false;
         if (n & 1) std::swap(a, b);  // an odd count leaves the state in the second buffer
         nsteps -= n;
     }
-    if (stop && after && st == PRC_OK) HIP_TRY(hipEventRecord(after, s));
+    if (!track && st == PRC_OK) {
+        if (stop) HIP_TRY(hipEventRecord(stop, s));
+        if (after) HIP_TRY(hipEventRecord(after, s));
+    } else if (stop && after && st == PRC_OK) {
+        HIP_TRY(hipEventRecord(after, s));
+    }
     if (track && st == PRC_OK) {
         HIP_TRY(hipEventRecord(d->last, s));
         d->has_last = true;

@@ -83,12 +83,15 @@ def test_resident_rejects_grids_beyond_the_lds():
             capi.prc_set_tile(p, RESIDENT)
 
 
-def test_resident_steps_captured_by_the_caller():
+@pytest.mark.parametrize("mode", ["plain", "timed", "kernel_only"])
+def test_resident_steps_captured_by_the_caller(mode):
     """A caller captures prc_step (one resident launch of 64 steps) into a
     graph of its own and replays it three times, with eager work and host
     synchronisation between the replays: the base of the step tags lives on
     the device, so every replay continues the count, and after each replay
-    the state equals that of 64 more single steps, bit for bit."""
+    the state equals that of 64 more single steps, bit for bit.  The same
+    for prc_step_timed (its events become event-record nodes of the graph,
+    and each replay's pair gives a positive elapsed time)."""
     from paper_2208_03562_amd import capi, solver
     nx, ny = 200, 90
     s = spec(nx, ny, 2.0, 0.5, omega_nu=1.3, u_lid=0.05, storage="f32")
@@ -110,10 +113,17 @@ def test_resident_steps_captured_by_the_caller():
         sol = solver.Solver(p, stream=stream)
         sol.set_state(noise)
         sol.step(2)  # the first resident call sets up its counters, outside capture
+        ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        ev[0].record(stream)
+        ev[1].record(stream)
         stream.synchronize()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g, stream=stream):
-            sol.step(64)  # 64 steps: the newest state is back in the same buffer
+            # 64 steps: the newest state is back in the same buffer
+            if mode == "plain":
+                sol.step(64)
+            else:
+                sol.step_timed(64, *ev, kernel_only=(mode == "kernel_only"))
         for k in range(3):
             g.replay()
             sol.residual()  # synchronises; reports a lost wait
@@ -121,6 +131,8 @@ def test_resident_steps_captured_by_the_caller():
             torch.cuda.synchronize()
             assert float(scratch) == float(1 << 20)
             assert bool((sol.get_state() == want[k]).all()), k
+            if mode != "plain":
+                assert ev[0].elapsed_time(ev[1]) > 0.0
     finally:
         capi.prc_set_tile(p, -1)
         capi.prc_release_graphs()
