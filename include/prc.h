@@ -406,13 +406,13 @@ prc_status prc_batch_solve(prc_batch *b, double tol, int64_t check_every, int64_
                            int64_t *hist_len, hipStream_t stream);
 
 /* Autotuner for the batch sweep: time each tile shape a batch can use
- * (indices 0 .. 6 of prc_tune: the single-step shapes and the two-step 64 x 8
- * and 32 x 16) on the current members, sweeping f_a into f_b (f_a, which holds
+ * (indices 0 .. 7 of prc_tune: the single-step shapes and the two-step 64 x 8,
+ * 32 x 16 and 64 x 16) on the current members, sweeping f_a into f_b (f_a, which holds
  * the state, is only read), and keep the fastest for this batch.  tile_out
  * (may be NULL) receives it.  Synchronises the stream. */
 prc_status prc_batch_tune(prc_batch *b, int32_t *tile_out, hipStream_t stream);
 
-/* Use tile shape `tile` (0 .. 6, as for prc_batch_tune) for this batch's
+/* Use tile shape `tile` (0 .. 7, as for prc_batch_tune) for this batch's
  * sweeps.  Host only. */
 prc_status prc_batch_set_tile(prc_batch *b, int32_t tile);
 
@@ -454,7 +454,7 @@ typedef struct {
                              and a velocity snapshot (16 B/node) each */
     int32_t max_active;   /* at most this many requests in the batch; 0 = no
                              limit, 1 = one at a time */
-    int32_t tile;         /* sweep tile shape (0 .. 6, as for prc_batch_tune),
+    int32_t tile;         /* sweep tile shape (0 .. 7, as for prc_batch_tune),
                              -1 for the default */
 } prc_serve_config;
 

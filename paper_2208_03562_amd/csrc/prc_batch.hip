@@ -226,7 +226,10 @@ static prc_status launch_batch_shape(const prc_batch &b, int v, int parity, hipS
     const int nt = b.ntiles[v];
     const int per_xcd = (nt + kXcds - 1) / kXcds;
     if constexpr (STEPS == 2) {
-        hipLaunchKernelGGL((k_sweep_batch2<ST, BC, TX, TY, FORCE, ALL>), dim3(per_xcd * kXcds),
+        // 1024-thread tiles: the instance for states streamed from HBM, as
+        // for single problems of that size
+        hipLaunchKernelGGL((k_sweep_batch2<ST, BC, TX, TY, FORCE, ALL, TX * TY == 1024>),
+                           dim3(per_xcd * kXcds),
                            dim3(TX * TY), 0, s, (const BatchTile *)b.d_tiles[v].ptr, nt, per_xcd,
                            (const BatchMember<CT> *)b.d_members.ptr, parity);
     } else {
@@ -266,6 +269,9 @@ static prc_status launch_batch_sweep(const prc_batch &b, int parity, bool two, h
     case 6:
         return two ? launch_batch_variants<ST, BC, 32, 16, 2>(b, parity, s)
                    : launch_batch_variants<ST, BC, 32, 16, 1>(b, parity, s);
+    case 7:
+        return two ? launch_batch_variants<ST, BC, 64, 16, 2>(b, parity, s)
+                   : launch_batch_variants<ST, BC, 64, 16, 1>(b, parity, s);
     default: return launch_batch_variants<ST, BC, 64, 4, 1>(b, parity, s);
     }
 }

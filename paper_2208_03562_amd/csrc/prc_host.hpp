@@ -187,9 +187,10 @@ constexpr TileShape kTiles[] = {{64, 4, 1},  {64, 8, 1},  {128, 4, 1}, {32, 8, 1
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 constexpr int kNumSingleStepTiles = 5;  // indices below this advance one step
 // Batches use the shapes below this index: the single-step ones and the
-// two-step shapes whose single-step twin has the same tile (64 x 8 -> 1,
-// 32 x 16 -> 4), so that one tile list serves both.
-constexpr int kNumBatchTiles = 7;
+// two-step shapes, each of which has a single-step twin of the same tile
+// (64 x 8 -> 1, 32 x 16 -> 4; 64 x 16 has a 1024-thread single-step instance
+// of its own for batches), so that one tile list serves both.
+constexpr int kNumBatchTiles = 8;
 constexpr int kResidentTile = 9;
 
 // Whether the resident sweep can run problem p on the current device

@@ -307,8 +307,10 @@ __global__ void __launch_bounds__(TX *TY)
 }
 
 // A tile list over many problems (batches), as k_sweep_batch: two steps from
-// buf[parity] into buf[parity ^ 1].
-template <typename ST, int BC, int TX, int TY, bool FORCE, bool ALL>
+// buf[parity] into buf[parity ^ 1].  STREAMED as for k_sweep2 (the instance
+// keeps both load orders behind the members' run-time flag, so either
+// instance gives the same bits).
+template <typename ST, int BC, int TX, int TY, bool FORCE, bool ALL, bool STREAMED>
 __global__ void __launch_bounds__(TX *TY)
     __attribute__((amdgpu_waves_per_eu(two_step_waves_per_simd<ST, TX, TY>())))
     k_sweep_batch2(const BatchTile *__restrict__ tiles, int ntiles, int tiles_per_xcd,
@@ -318,8 +320,9 @@ __global__ void __launch_bounds__(TX *TY)
     if (t >= ntiles) return;
     const BatchTile tl = tiles[t];
     const BatchMember<typename Mem<ST>::CT> &m = members[tl.member];
-    sweep2_tile<ST, BC, TX, TY, FORCE, ALL, false>(m.c, m.buf[parity], const_cast<void *>(m.buf[parity ^ 1]),
-                                            tl.x0, tl.y0);
+    sweep2_tile<ST, BC, TX, TY, FORCE, ALL, STREAMED>(m.c, m.buf[parity],
+                                                      const_cast<void *>(m.buf[parity ^ 1]), tl.x0,
+                                                      tl.y0);
 }
 
 }  // namespace prc

@@ -161,11 +161,12 @@ def test_batch_host_checks():
             capi.prc_batch_solve(b, 1e-6, 100, 250)   # max_steps not a multiple
         with pytest.raises(capi.PrcError):
             capi.prc_batch_solve(b, 1e-6, 101, 202)   # odd check interval
-        for t in (-1, 7):
+        for t in (-1, 8):
             with pytest.raises(capi.PrcError):
                 capi.prc_batch_set_tile(b, t)
         capi.prc_batch_set_tile(b, 2)
         capi.prc_batch_set_tile(b, 6)      # two steps per launch
+        capi.prc_batch_set_tile(b, 7)      # 64 x 16, two steps per launch
     finally:
         capi.prc_batch_destroy(b)
 
@@ -186,7 +187,7 @@ def serve_cfg(**kw):
 
 
 @pytest.mark.parametrize("kw", [dict(check_every=99), dict(check_every=0), dict(max_steps=150),
-                                dict(tol=-1.0), dict(tile=7), dict(hbm_budget=100),
+                                dict(tol=-1.0), dict(tile=8), dict(hbm_budget=100),
                                 dict(storage=7), dict(bc=4)])
 def test_serve_rejects_bad_config(kw):
     with pytest.raises(capi.PrcError) as e:
@@ -261,7 +262,8 @@ def test_batch_tile_range():
     try:
         capi.prc_batch_set_tile(b, 5)    # two steps per launch, FP64 included
         capi.prc_batch_set_tile(b, 4)
+        capi.prc_batch_set_tile(b, 7)    # 64 x 16, two steps per launch
         with pytest.raises(capi.PrcError):
-            capi.prc_batch_set_tile(b, 7)  # not a batch shape
+            capi.prc_batch_set_tile(b, 8)  # not a batch shape
     finally:
         capi.prc_batch_destroy(b)

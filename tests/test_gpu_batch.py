@@ -44,7 +44,7 @@ def alone(s, tol, K, max_steps):
     return sol, st, n, hist
 
 
-@pytest.mark.parametrize("tile", [None, 1, 2, 5, 6])
+@pytest.mark.parametrize("tile", [None, 1, 2, 5, 6, 7])
 def test_batch_solve_is_bitwise_the_single_solve(torch_cuda, tile):
     from paper_2208_03562_amd import solver
     tol, K, max_steps = 1e-4, 100, 1600
@@ -110,7 +110,8 @@ def test_member_joining_later_and_removal(torch_cuda):
 
 
 @pytest.mark.parametrize("storage,tile", [("f64", None), ("f16", None), ("bf16", None),
-                                          ("f16", 5), ("bf16", 6), ("f64", 5), ("f64", 6)])
+                                          ("f16", 5), ("bf16", 6), ("f64", 5), ("f64", 6),
+                                          ("f16", 7), ("bf16", 7), ("f64", 7)])
 def test_batch_other_storage_types(torch_cuda, storage, tile):
     from paper_2208_03562_amd import capi, solver
     specs = [dict(MIX[0], storage=storage), dict(MIX[1], storage=storage),
@@ -126,6 +127,37 @@ def test_batch_other_storage_types(torch_cuda, storage, tile):
         assert (status[i], steps[i], hists[i]) == (st, n, hist)
         assert bool((b.members[i].get_state() == sol.get_state()).all())
     b.close()
+
+
+@pytest.mark.parametrize("tile", [6, 7])
+def test_batch_streamed_from_hbm_gives_the_single_step_bits(torch_cuda, tile):
+    """Three 2048 x 1024 FP32 members: together their states exceed the
+    last-level cache, so the batch stores non-temporally (and the 64 x 16
+    shape runs its instance for streamed states); ten steps give each
+    member the bits of ten single steps of it alone."""
+    from paper_2208_03562_amd import capi, solver
+    specs = [spec(2048, 1024, r, g, omega_nu=w, u_lid=0.05, storage="f32")
+             for r, g, w in ((2.0, 0.5, 1.3), (0.5, 0.2, 1.1), (1.0, 1.0, 1.7))]
+    b = solver.Batch()
+    b.set_tile(tile)
+    for k, s in enumerate(specs):
+        i = b.add(lib_params(s))
+        b.members[i].set_state(workloads.deviation_noise(s["nx"], s["ny"], 40 + k, 1e-3))
+    b.step(10)
+    torch_cuda.cuda.synchronize()
+    got = [m.get_state() for m in b.members]
+    b.close()
+    del b
+    for k, s in enumerate(specs):
+        p = lib_params(s)
+        capi.prc_set_tile(p, 1)  # single steps
+        sol = solver.Solver(p)
+        sol.set_state(workloads.deviation_noise(s["nx"], s["ny"], 40 + k, 1e-3))
+        sol.step(10)
+        assert bool((sol.get_state() == got[k]).all()), k
+        capi.prc_set_tile(p, -1)
+        del sol
+    capi.prc_release_graphs()
 
 
 def test_batch_member_against_oracle(O, torch_cuda):
