@@ -413,7 +413,9 @@ prc_status prc_batch_solve(prc_batch *b, double tol, int64_t check_every, int64_
 prc_status prc_batch_tune(prc_batch *b, int32_t *tile_out, hipStream_t stream);
 
 /* Use tile shape `tile` (0 .. 7, as for prc_batch_tune) for this batch's
- * sweeps.  Host only. */
+ * sweeps.  Without it (or prc_batch_tune) a batch sweeps two steps per
+ * launch on 32 x 16 tiles, or on 64 x 16 tiles once its members' states
+ * together exceed 160 MB (FP32 and 16-bit storage).  Host only. */
 prc_status prc_batch_set_tile(prc_batch *b, int32_t tile);
 
 /* ---- Serving: steady-state solve requests with continuous batching -----
