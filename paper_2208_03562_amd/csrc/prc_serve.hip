@@ -288,9 +288,7 @@ prc_status check_config(const prc_serve_config *cfg)
     if (cfg->max_steps < 0 || cfg->max_steps % cfg->check_every)
         return fail(PRC_EINVAL, "max_steps must be a non-negative multiple of check_every");
     if (!(cfg->tol >= 0.0)) return fail(PRC_EINVAL, "tol must be >= 0");
-    if (cfg->tile < -1 || cfg->tile >= kNumBatchTiles ||
-        (cfg->tile >= 0 && kTiles[cfg->tile].steps == 2 && cfg->storage == PRC_F64))
-        return fail(PRC_EINVAL, "tile out of range");
+    if (cfg->tile < -1 || cfg->tile >= kNumBatchTiles) return fail(PRC_EINVAL, "tile out of range");
     if (cfg->hbm_budget < 4096) return fail(PRC_EINVAL, "hbm_budget too small");
     if (cfg->max_active < 0) return fail(PRC_EINVAL, "max_active < 0");
     return PRC_OK;

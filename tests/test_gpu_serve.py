@@ -134,10 +134,12 @@ def test_online_server_rejects_other_storage_and_stops_mid_run():
         srv.close()  # stops after the current interval; the long request is dropped
 
 
-def test_served_fp64_requests_match_the_oracle(O):
+@pytest.mark.parametrize("tile", [-1, 4, 7])
+def test_served_fp64_requests_match_the_oracle(O, tile):
     """An FP64 server, two small cavities submitted together: steps, status
     and final velocity against the oracle's solve with the same tol and check
-    interval (round-off only)."""
+    interval (round-off only), on the default sweep shape, a single-step one
+    and the 64 x 16 two-step one."""
     import numpy as np
     from paper_2208_03562_amd import capi, serving
     from tests.common import oracle_params
@@ -146,7 +148,7 @@ def test_served_fp64_requests_match_the_oracle(O):
     tol, k, mx = 1e-9, 200, 60000
     served = serving.serve_online([lib_params(s) for s in specs], [0.0, 0.0],
                                   storage=capi.PRC_F64, tol=tol, check_every=k, max_steps=mx,
-                                  hbm_budget=16 << 20, fields=True)
+                                  hbm_budget=16 << 20, fields=True, tile=tile)
     for s, r in zip(specs, served):
         po = oracle_params(O, s)
         ft = O.rest_state(po)
