@@ -378,7 +378,7 @@ PMC_COPY_BYTES = 256 * 2 ** 20  # bytes read and bytes written by pmc_run's copy
 PMC_SMALL = workloads.CAVITY_1024x512_F32
 PMC_BIG = (workloads.CAVITY_4096x2048_F32, workloads.CAVITY_4096x2048_MA002["f16"],
            workloads.CAVITY_4096x2048_MA002["bf16"], workloads.CAVITY_4096x2048_MA002["f64"])
-# resident launches of the driver's timed call (20 steps), counted first
+# resident launches as long as the default timed call (20 steps), counted first
 PMC_SHORT_STEPS, PMC_SHORT_LAUNCHES = 20, 5
 RESIDENT_TILE = 9
 
@@ -391,7 +391,7 @@ def pmc_run(steps: int):
     """Fixed workload of the counter runs: a plain device copy of 256 MiB
     each way (the reference for scaling byte counters); on the 1024 x 512
     FP32 cavity PMC_SHORT_LAUNCHES resident launches of PMC_SHORT_STEPS steps
-    (the launch the driver's `--steps 20` call times) and then the tuner,
+    (the launch a `--steps 20` call times) and then the tuner,
     which launches every sweep instance (the resident sweep in 1000-step
     launches); on each 4096 x 2048 grid the tuner.  `steps` is unused (kept
     for the command line)."""
@@ -766,8 +766,8 @@ def main():
     main_roof = roofline_of(w, main_res, w.storage)
     wc = workloads.CAVITY_1024x512_F32_MA006
     comp = run_gpu(wc, args.steps, args.warmup)
-    # steady state: the survey's recipe for this cavity (1000-step warm-up
-    # and more, at least 10,000 timed steps, checks every 1000 inside)
+    # steady state: 12,000 timed steps after a 2,000-step warm-up, checks
+    # every 1000 inside (the cavity's residual interval)
     steady = run_gpu(w, STEADY_STEPS, STEADY_WARMUP)
     steady_roof = roofline_of(w, steady, w.storage)
     big = {}
